@@ -1,0 +1,305 @@
+"""Pins of the CPU oracle against facts fixed by the paper and by mathematics.
+
+Nothing here retypes the oracle's own formulas: projections are checked with
+exact rational arithmetic on an independent bfloat16 decode, bit layouts with
+hand-built weight matrices whose projections are known coordinates, candidate
+sets and rankings with a dense formulation, and the Euclidean step with
+SciPy's distance routine and the brute-force special case (one table, no
+bucket bits, K >= N: cascade hashing reduces to exact 2-NN + ratio test).
+"""
+from fractions import Fraction
+
+import numpy as np
+import pytest
+from scipy.spatial.distance import cdist
+
+from paper_2505_22089_amd import synth
+
+L, M = 6, 8
+
+
+def bf16_exact(bits: int) -> Fraction:
+    """Exact value of a bfloat16 bit pattern, decoded from sign/exponent/fraction."""
+    s, e, f = bits >> 15, (bits >> 7) & 0xFF, bits & 0x7F
+    assert e != 0xFF
+    if e == 0:
+        v = Fraction(f, 1) * Fraction(2) ** (-126 - 7)
+    else:
+        v = Fraction(128 + f, 1) * Fraction(2) ** (e - 127 - 7)
+    return -v if s else v
+
+
+def code_int(words) -> int:
+    return sum(int(w) << (32 * k) for k, w in enumerate(words))
+
+
+@pytest.fixture(scope="module")
+def small():
+    rng = np.random.default_rng(5)
+    A = synth.sift_like(rng, 300)
+    B = np.concatenate([synth.noisy_copy(rng, A[:150]), synth.sift_like(rng, 150)])
+    B = B[rng.permutation(300)]
+    W = synth.projection_weights(42, 128 + L * M)
+    mu = synth.centring_vector([A, B])
+    return A, B, W, mu
+
+
+def test_weights_are_rne_bf16_of_the_normal_draws():
+    z = np.random.default_rng(42).standard_normal((176, 128))
+    W = synth.projection_weights(42, 176)
+    for r in range(0, 176, 7):
+        for d in range(0, 128, 5):
+            q = bf16_exact(int(W[r, d]))
+            zz = Fraction(float(z[r, d]))
+            if q == 0:
+                assert abs(zz) < Fraction(2) ** -16 * (1 + Fraction(1, 256))
+                continue
+            # q has 8 significant bits and is within half an ulp of z
+            e = abs(q).numerator.bit_length() - abs(q).denominator.bit_length()
+            ulp = Fraction(2) ** (e - 7) if abs(q) >= Fraction(2) ** e else Fraction(2) ** (e - 8)
+            assert abs(q - zz) <= ulp / 2
+
+
+def test_projection_is_exact_rational(orc, small):
+    A, _, W, mu = small
+    P = orc.project(A, W, mu)
+    rng = np.random.default_rng(0)
+    Wq = [[bf16_exact(int(W[r, d])) for d in range(128)] for r in range(W.shape[0])]
+    for _ in range(200):
+        i, r = int(rng.integers(A.shape[0])), int(rng.integers(W.shape[0]))
+        exact = sum(Wq[r][d] * (int(A[i, d]) - int(mu[d])) for d in range(128))
+        assert Fraction(float(P[i, r])) == exact
+        # and the exactness argument: a multiple of 2^-23 below 2^20 in magnitude
+        assert (exact * 2 ** 23).denominator == 1 and abs(exact) < 2 ** 20
+
+
+def test_bit_layout_with_coordinate_rows(orc):
+    """Row r = +-e_{d(r)}: projection r is +-(x_d - mu_d), so every bit is known by hand."""
+    rng = np.random.default_rng(11)
+    R = 128 + L * M
+    dims = rng.integers(0, 128, size=R)
+    sign = np.where(rng.random(R) < 0.5, -1.0, 1.0)
+    W = np.zeros((R, 128), dtype=np.uint16)
+    for r in range(R):
+        W[r, dims[r]] = 0xBF80 if sign[r] < 0 else 0x3F80     # -1.0 / +1.0 in bf16
+    X = rng.integers(0, 256, size=(64, 128)).astype(np.uint8)
+    mu = rng.integers(0, 256, size=128).astype(np.uint8)
+    codes, ids = orc.hash_codes(X, W, mu, L, M)
+    proj = sign[None, :] * (X[:, dims].astype(np.int64) - mu[dims].astype(np.int64))
+    bits = proj > 0
+    for i in range(64):
+        for w in range(4):
+            expect = sum(1 << k for k in range(32) if bits[i, 32 * w + k])
+            assert codes[i, w] == expect
+        for t in range(L):
+            expect = sum(1 << j for j in range(M) if bits[i, 128 + M * t + j])
+            assert ids[i, t] == expect
+
+
+def test_descriptor_equal_to_mu_gives_zero_code(orc, small):
+    _, _, W, mu = small
+    X = np.stack([mu, mu])
+    codes, ids = orc.hash_codes(X, W, mu, L, M)
+    assert not codes.any() and not ids.any()
+
+
+def test_negated_row_flips_its_bit(orc, small):
+    A, _, W, mu = small
+    P = orc.project(A, W, mu)
+    c0, i0 = orc.hash_codes(A, W, mu, L, M)
+    W2 = W.copy()
+    for r in (3, 77, 131, 175):
+        W2[r] ^= 0x8000
+    c1, i1 = orc.hash_codes(A, W2, mu, L, M)
+    for r in (3, 77):
+        b0 = (c0[:, r // 32] >> (r % 32)) & 1
+        b1 = (c1[:, r // 32] >> (r % 32)) & 1
+        nz = P[:, r] != 0
+        assert np.all(b0[nz] != b1[nz])
+    for r in (131, 175):
+        t, j = (r - 128) // M, (r - 128) % M
+        b0 = (i0[:, t] >> j) & 1
+        b1 = (i1[:, t] >> j) & 1
+        nz = P[:, r] != 0
+        assert np.all(b0[nz] != b1[nz])
+
+
+def test_sign_projection_collision_probability(orc):
+    """Charikar: P[bit_r(x) != bit_r(y)] = angle(x - mu, y - mu) / pi."""
+    rng = np.random.default_rng(3)
+    n = 3000
+    X = synth.sift_like(rng, n)
+    Y = synth.sift_like(rng, n)
+    mu = synth.centring_vector([X, Y])
+    W = synth.projection_weights(7, 128 + L * M)
+    cx, _ = orc.hash_codes(X, W, mu, L, M)
+    cy, _ = orc.hash_codes(Y, W, mu, L, M)
+    h = np.array([bin(code_int(a) ^ code_int(b)).count("1") for a, b in zip(cx, cy)])
+    xc = X.astype(np.float64) - mu
+    yc = Y.astype(np.float64) - mu
+    cos = (xc * yc).sum(1) / np.sqrt((xc * xc).sum(1) * (yc * yc).sum(1))
+    theta = np.arccos(np.clip(cos, -1, 1))
+    # the 128 rows are a fixed draw, so compare averages over many pairs
+    err = h.mean() - (128 * theta / np.pi).mean()
+    assert abs(err) < 0.6, err
+
+
+def test_tables_are_complete_stable_buckets(orc, small):
+    A, _, W, mu = small
+    codes, ids = orc.hash_codes(A, W, mu, L, M)
+    offsets, members = orc.tables(ids, M)
+    n = A.shape[0]
+    for t in range(L):
+        assert offsets[t, 0] == 0 and offsets[t, -1] == n
+        assert np.all(np.diff(offsets[t]) >= 0)
+        assert np.array_equal(np.sort(members[t]), np.arange(n))
+        assert np.array_equal(members[t], np.argsort(ids[:, t], kind="stable"))
+        for b in range(1 << M):
+            mem = members[t, offsets[t, b]:offsets[t, b + 1]]
+            assert np.all(ids[mem, t] == b) and np.all(np.diff(mem) > 0)
+
+
+def dense_topk(cq, iq, cd, idd, K):
+    """Candidates as the dense mask {j : some table shares the bucket}, ranked by (h, j)."""
+    out = []
+    qi = [code_int(c) for c in cq]
+    di = [code_int(c) for c in cd]
+    for i in range(len(qi)):
+        mask = (iq[i][None, :] == idd).any(axis=1)
+        keys = sorted((bin(qi[i] ^ di[j]).count("1"), j) for j in np.nonzero(mask)[0])
+        out.append(keys[:K])
+    return out
+
+
+@pytest.mark.parametrize("m,K", [(8, 8), (3, 5), (1, 40)])
+def test_candidates_and_ranking_match_dense_formulation(orc, small, m, K):
+    A, B, W0, mu = small
+    A, B = A[:120], B[:120]
+    W = W0[:128 + L * m]
+    hq = orc.hash_image(A, W, mu, L, m)
+    hd = orc.hash_image(B, W, mu, L, m)
+    out, topk, nc = orc.match_pair(hq, hd, L, m, K, want_topk=True)
+    dense = dense_topk(hq.codes, hq.ids, hd.codes, hd.ids, K)
+    total = 0
+    for i in range(len(A)):
+        expect = [(h << 24) | j for h, j in dense[i]] + [0xFFFFFFFF] * (K - len(dense[i]))
+        assert list(topk[i]) == expect
+        total += sum(1 for _ in dense[i])
+    if K >= 120:
+        assert nc == total
+
+
+def test_hamming_is_symmetric_and_zero_on_self(orc, small):
+    A, B, W, mu = small
+    A, B = A[:40], B[:40]
+    Wm = W[:128]
+    hq = orc.hash_image(A, Wm, mu, 1, 0)
+    hd = orc.hash_image(B, Wm, mu, 1, 0)
+    _, t_qd, _ = orc.match_pair(hq, hd, 1, 0, 40, want_topk=True)
+    _, t_dq, _ = orc.match_pair(hd, hq, 1, 0, 40, want_topk=True)
+    H1 = np.zeros((40, 40), int)
+    H2 = np.zeros((40, 40), int)
+    for i in range(40):
+        for k in t_qd[i]:
+            H1[i, k & 0xFFFFFF] = k >> 24
+        for k in t_dq[i]:
+            H2[i, k & 0xFFFFFF] = k >> 24
+    assert np.array_equal(H1, H2.T)
+    _, t_self, _ = orc.match_pair(hq, hq, 1, 0, 40, want_topk=True)
+    for i in range(40):
+        assert (t_self[i] >> 24).min() == 0
+        hs = {int(k & 0xFFFFFF): int(k >> 24) for k in t_self[i]}
+        assert hs[i] == 0
+        for j in range(40):   # triangle inequality through the db codes
+            assert hs[j] <= H1[i].min() + H1[j].min() + 128  # trivially bounded
+            for l in range(0, 40, 7):
+                assert hs[j] <= H1[i, l] + H1[j, l]
+
+
+def two_nn_ratio(Xq, Xd, a, b):
+    D = cdist(Xq.astype(np.float64), Xd.astype(np.float64), "sqeuclidean").astype(np.int64)
+    out = np.full(len(Xq), -1, np.int32)
+    if Xd.shape[0] < 2:
+        return out
+    order = np.argsort(D, axis=1, kind="stable")
+    d1 = D[np.arange(len(Xq)), order[:, 0]]
+    d2 = D[np.arange(len(Xq)), order[:, 1]]
+    ok = b * b * d1 < a * a * d2
+    out[ok] = order[ok, 0]
+    return out
+
+
+def test_single_bucket_reduces_to_exhaustive_2nn(orc, small):
+    A, B, W, mu = small
+    Wm = W[:128]
+    hq = orc.hash_image(A, Wm, mu, 1, 0)
+    hd = orc.hash_image(B, Wm, mu, 1, 0)
+    out, _, nc = orc.match_pair(hq, hd, 1, 0, B.shape[0], ratio=(4, 5))
+    ref = two_nn_ratio(A, B, 4, 5)
+    assert np.array_equal(out, ref)
+    assert nc == A.shape[0] * B.shape[0]
+    assert np.array_equal(orc.bruteforce(A, B, (4, 5)), ref)
+    assert np.array_equal(orc.bruteforce(A, B, (2, 3)), two_nn_ratio(A, B, 2, 3))
+    # ratios near 1 make the verdict hinge on the exact second-nearest distance
+    for ab in [(9, 10), (99, 100), (1, 1)]:
+        ref = two_nn_ratio(A, B, *ab)
+        out, _, _ = orc.match_pair(hq, hd, 1, 0, B.shape[0], ratio=ab)
+        assert np.array_equal(out, ref)
+        assert np.array_equal(orc.bruteforce(A, B, ab), ref)
+
+
+def test_ratio_test_consistency(orc):
+    wl = synth.config1()
+    H = orc.hash_workload(wl)
+    out, topk, _ = orc.match_pair(H[0], H[1], wl.L, wl.m, wl.K, want_topk=True)
+    a, b = wl.ratio
+    A, B = wl.images
+    for i in range(A.shape[0]):
+        js = [int(k & 0xFFFFFF) for k in topk[i] if k != 0xFFFFFFFF]
+        if len(js) < 2:
+            assert out[i] == -1
+            continue
+        d = sorted((int(((A[i].astype(np.int64) - B[j]) ** 2).sum()), j) for j in js)
+        passes = b * b * d[0][0] < a * a * d[1][0]
+        assert (out[i] == d[0][1]) if passes else (out[i] == -1)
+
+
+def test_planted_correspondences_are_recovered(orc):
+    wl = synth.config1()
+    H = orc.hash_workload(wl)
+    out, _, nc = orc.match_pair(H[0], H[1], wl.L, wl.m, wl.K)
+    gt = {int(a): int(b) for a, b in wl.gt}
+    recall = np.mean([out[a] == b for a, b in gt.items()])
+    matched = np.nonzero(out >= 0)[0]
+    precision = np.mean([gt.get(int(a), -2) == out[a] for a in matched])
+    assert recall > 0.9 and precision > 0.98
+
+
+def test_self_pair_is_identity(orc, small):
+    A, _, W, mu = small
+    h = orc.hash_image(A, W, mu, L, M)
+    out, topk, _ = orc.match_pair(h, h, L, M, 8, want_topk=True)
+    assert np.array_equal(out, np.arange(A.shape[0]))
+
+
+def test_duplicates_tie_by_index_and_fail_ratio(orc, small):
+    A, B, W, mu = small
+    D = np.concatenate([B[:10], np.repeat(A[:1], 5, axis=0), B[10:40]])
+    hq = orc.hash_image(A[:1], W, mu, L, M)
+    hd = orc.hash_image(D, W, mu, L, M)
+    out, topk, _ = orc.match_pair(hq, hd, L, M, 8, want_topk=True)
+    assert list(topk[0][:5]) == [j for j in range(10, 15)]   # h = 0, j ascending
+    assert out[0] == -1                                       # d1 == d2 == 0
+
+
+def test_empty_and_single_images(orc, small):
+    A, B, W, mu = small
+    h0 = orc.hash_image(A[:0], W, mu, L, M)
+    h1 = orc.hash_image(B[:1], W, mu, L, M)
+    hq = orc.hash_image(A[:5], W, mu, L, M)
+    out, _, nc = orc.match_pair(hq, h0, L, M, 8)
+    assert np.all(out == -1) and nc == 0
+    out, _, _ = orc.match_pair(hq, h1, L, M, 8)
+    assert np.all(out == -1)
+    out, _, _ = orc.match_pair(h0, hq, L, M, 8)
+    assert out.shape == (0,)
