@@ -1,0 +1,283 @@
+/*
+ * chm.h -- C-ABI of the MI355X (gfx950) cascade-hashing feature matcher.
+ *
+ * The library implements, as hand-written HIP kernels, cascade-hashing
+ * matching of image pairs (paper Sec. 2.3.1, steps (1)-(4)): sign-of-random-
+ * projection codes of n = 128 bits and L tables of 2^m buckets per image,
+ * same-bucket candidate lookup, Hamming ranking to the top K, exact integer
+ * Euclidean re-rank of those K and the ratio test; the block-row pipeline of
+ * Sec. 2.3.2 (load descriptors and build codes/tables on load, match the
+ * pairs of a block, free what the next block row no longer needs); and the
+ * host-side MBR block schedule of Sec. 2.2 with GPS ordering (Appendix A).
+ *
+ * Conventions shared by every call:
+ *  - Descriptors are 128-d uint8 rows (SIFT, Sec. 2.4), row-major, 128 B each.
+ *  - "d_" pointers are device (HBM) pointers, "h_" pointers are host pointers.
+ *    Device memory is owned by the caller: the library never allocates device
+ *    memory, it sub-allocates inside the arena the caller hands to
+ *    chm_store_create.  Streams are passed as void* (a hipStream_t; NULL is
+ *    the null stream).  Work is enqueued on the given stream; host arrays are
+ *    only read during the call.
+ *  - Every call returns a chm_status (0 = CHM_OK).  On error, outputs are
+ *    unspecified and chm_last_error() returns a message for the calling
+ *    thread.  HIP runtime failures map to CHM_E_HIP; asynchronous kernel
+ *    faults surface at a later call or at stream synchronisation.
+ *  - Results never depend on the match mode, the stream, the tuning or the
+ *    schedule: they are the unique output of the method as specified below.
+ */
+#ifndef CHM_H
+#define CHM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define CHM_ABI_VERSION 1
+#define CHM_DIM 128       /* descriptor dimension (SIFT) */
+#define CHM_CODE_BITS 128 /* n, bits of the long code (Sec. 2.3.1 step (2), n = 128) */
+#define CHM_MAX_FEATS 65535
+
+typedef enum chm_status {
+  CHM_OK = 0,
+  CHM_E_INVALID_ARG = -1,  /* a size, pointer or parameter is out of range */
+  CHM_E_UNSUPPORTED = -2,  /* a valid request this build does not support */
+  CHM_E_CAPACITY = -3,     /* the arena (or a cap) cannot hold what was asked */
+  CHM_E_NOT_RESIDENT = -4, /* a pair names an image that is not loaded */
+  CHM_E_HIP = -5,          /* a HIP runtime call failed */
+  CHM_E_INTERNAL = -6
+} chm_status;
+
+enum { CHM_PROJ_BF16 = 0, CHM_PROJ_FP32 = 1 };
+enum { CHM_MATCH_PLAIN = 0, CHM_MATCH_BATCHED = 1 };
+
+/* Parameters of cascade hashing (Sec. 2.3.1; defaults in the paper:
+ * L = 6, m = 8, n = 128, K = 8; ratio threshold t_r, Sec. 3.2). */
+typedef struct chm_config {
+  uint32_t abi_version;   /* must be CHM_ABI_VERSION */
+  int32_t num_tables;     /* L, 1..8 */
+  int32_t bucket_bits;    /* m, 0..8 (0 = one bucket: every db point is a candidate) */
+  int32_t top_k;          /* K, 1..32: candidates kept by Hamming ranking */
+  int32_t ratio_num;      /* t_r = ratio_num / ratio_den, 0 < num <= den <= 46340 */
+  int32_t ratio_den;
+  int32_t proj_precision; /* CHM_PROJ_BF16 or CHM_PROJ_FP32 (MFMA input type) */
+  int32_t reserved;       /* must be 0 */
+  double fixup_rel;       /* a projection p is recomputed in fp64 when
+                             |p| < fixup_rel * ||W_r||_2 * ||x - mu||_2;
+                             must lie in [1e-4, 0.5] (1e-3 recommended) */
+} chm_config;
+
+/* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-3). */
+void chm_config_default(chm_config *cfg);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *chm_last_error(void);
+
+/* ABI version of the loaded library (CHM_ABI_VERSION it was built with). */
+int32_t chm_abi_version(void);
+
+/* ------------------------------------------------------------------ store
+ * A store keeps images resident in a caller-owned device arena: the raw
+ * descriptors and everything step (1)-(2) of Sec. 2.3.1 builds for them
+ * (long codes, bucket ids, lookup tables), as Sec. 2.3.2 step (1) loads a
+ * block's descriptors and computes their codes and bucket ids on load.
+ */
+typedef struct chm_store chm_store;
+
+/* Bytes of arena one image of n_feats descriptors occupies (descriptors,
+ * codes, bucket ids, norms, tables; 256-byte aligned sections). */
+chm_status chm_image_bytes(const chm_config *cfg, int32_t n_feats, uint64_t *out_bytes);
+
+/* Bytes of arena the store itself needs (projection matrix, counters). */
+chm_status chm_store_overhead_bytes(const chm_config *cfg, uint64_t *out_bytes);
+
+/* Creates a store.
+ *   cfg      : parameters (copied).
+ *   h_W      : host, (128 + L*m) x 128 bfloat16 bit patterns, row r is the
+ *              r-th random projection (rows 0..127 the long code, row
+ *              128 + m*t + j bit j of table t's bucket id).  Every value must
+ *              be 0 or of magnitude in [2^-16, 32) (the fp64 recompute is then
+ *              exact); otherwise CHM_E_INVALID_ARG.
+ *   h_mu     : host, 128 uint8, the centring vector subtracted before projection.
+ *   d_arena  : device, 256-byte aligned, arena_bytes long, owned by the caller
+ *              and not touched by anyone else while the store lives.
+ *   out      : receives the store.  The store copies W and mu into the arena
+ *              (enqueued on the null stream and completed before returning). */
+chm_status chm_store_create(const chm_config *cfg, const uint16_t *h_W, const uint8_t *h_mu,
+                            void *d_arena, uint64_t arena_bytes, chm_store **out);
+
+/* Destroys a store (synchronises the device first).  NULL is ignored. */
+void chm_store_destroy(chm_store *store);
+
+/* Loads `count` images (Sec. 2.3.2 step (1), Algorithm 1 "load"): copies each
+ * image's descriptors into the arena (host->device if descs_on_device == 0,
+ * device->device otherwise) and builds its long codes, bucket ids and
+ * lookup tables, with batched kernel launches for all images of the call.
+ *   image_ids : host, count distinct ids >= 0 not already resident.
+ *   descs     : host array of count pointers to n_feats[i] x 128 uint8 rows
+ *               (host memory should be pinned for an asynchronous copy).
+ *   n_feats   : host, 0..CHM_MAX_FEATS each.
+ * Errors: CHM_E_INVALID_ARG (duplicates, resident ids, bad sizes),
+ * CHM_E_CAPACITY (arena full; nothing of the call is loaded). */
+chm_status chm_store_load(chm_store *store, int32_t count, const int32_t *image_ids,
+                          const void *const *descs, const int32_t *n_feats,
+                          int32_t descs_on_device, void *stream);
+
+/* Rebuilds codes, bucket ids and tables of resident images from their
+ * descriptors (the hashing stage alone).  CHM_E_NOT_RESIDENT if one is not. */
+chm_status chm_store_rehash(chm_store *store, int32_t count, const int32_t *image_ids,
+                            void *stream);
+
+/* Frees resident images (Algorithm 1 "free"); their arena space is reused by
+ * later work on the same stream.  Plans that use them become invalid. */
+chm_status chm_store_evict(chm_store *store, int32_t count, const int32_t *image_ids);
+
+/* n_feats of a resident image, or -1 in *out if it is not resident. */
+chm_status chm_store_image_feats(const chm_store *store, int32_t image_id, int32_t *out);
+
+typedef struct chm_stats {
+  uint64_t h2d_bytes;        /* descriptor bytes copied host -> device */
+  uint64_t d2d_bytes;        /* descriptor bytes copied device -> device */
+  uint64_t resident_bytes;   /* arena bytes held by resident images now */
+  uint64_t resident_peak;    /* maximum of resident_bytes so far */
+  uint64_t fixups;           /* projections recomputed in fp64 (synchronises) */
+  int64_t images_loaded;
+  int64_t images_evicted;
+  int32_t resident_images;
+  int32_t reserved;
+} chm_stats;
+
+chm_status chm_store_stats(chm_store *store, chm_stats *out);
+
+/* Copies an image's internal arrays to caller device buffers (for tests):
+ *   d_codes   : n x 4 uint32 (bit r of the long code in word r/32, bit r%32)
+ *   d_ids     : n x 8 uint8 (byte t = bucket id of table t, bit j of it from
+ *               projection row 128 + m*t + j; bytes >= L are 0)
+ *   d_offsets : L x (2^m + 1) int32, bucket b of table t holds
+ *               members[t][offsets[t][b] .. offsets[t][b+1])
+ *   d_members : L x n uint16 db indices, ascending inside each bucket
+ *   d_norms   : n uint32, squared norm of each descriptor
+ * Any pointer may be NULL to skip that array. */
+chm_status chm_debug_image(chm_store *store, int32_t image_id, uint32_t *d_codes, uint8_t *d_ids,
+                           int32_t *d_offsets, uint16_t *d_members, uint32_t *d_norms,
+                           void *stream);
+
+/* ------------------------------------------------------------------ matching
+ * Steps (1)-(4) of Sec. 2.3.1 for directed pairs (query image q, db image d):
+ * for every descriptor x_i of q, the candidates are the set union over the L
+ * tables of d's points in x_i's bucket; they are ranked by (Hamming distance
+ * of the long codes, db index) and the first min(K, |C_i|) are kept; their
+ * squared Euclidean distances are computed exactly in integers; with d1 <= d2
+ * the two smallest and j1 the db index reaching d1, the output is j1 if
+ * ratio_den^2 * d1 < ratio_num^2 * d2 and -1 otherwise (also -1 when fewer
+ * than two candidates exist).
+ */
+typedef struct chm_plan chm_plan;
+
+/* Builds an executable plan for a pair list.
+ *   h_pairs       : host, n_pairs x 2 int32 (query image, db image), both
+ *                   resident (else CHM_E_NOT_RESIDENT); self pairs allowed.
+ *   h_out_offsets : host, n_pairs + 1 int64; pair p writes its n_q results to
+ *                   d_out[h_out_offsets[p] .. h_out_offsets[p+1]) which must
+ *                   have exactly n_q elements (else CHM_E_INVALID_ARG).
+ *   d_out         : device int32 output (db index or -1 per query descriptor).
+ *   d_topk        : device, NULL or K uint32 per output element: the ranked
+ *                   candidates as keys (hamming << 24) | db_index, 0xFFFFFFFF
+ *                   where fewer than K candidates exist (for tests).
+ *   mode          : CHM_MATCH_PLAIN (one launch per pair, host loop) or
+ *                   CHM_MATCH_BATCHED (all pairs in one persistent launch
+ *                   replayed from a captured HIP graph).
+ * The plan keeps its work list in the arena (CHM_E_CAPACITY if full) and
+ * stays valid until one of its images is evicted or the plan is destroyed. */
+chm_status chm_plan_create(chm_store *store, const int32_t *h_pairs, int32_t n_pairs,
+                           const int64_t *h_out_offsets, int32_t *d_out, uint32_t *d_topk,
+                           int32_t mode, void *stream, chm_plan **out);
+
+/* Enqueues the plan's matching on `stream`.  CHM_E_NOT_RESIDENT if an image
+ * of the plan was evicted since the plan was built. */
+chm_status chm_plan_execute(chm_plan *plan, void *stream);
+
+/* Frees the plan (synchronises the streams it ran on).  NULL is ignored. */
+void chm_plan_destroy(chm_plan *plan);
+
+/* One-shot matching: create + execute + destroy (synchronous). */
+chm_status chm_match_pairs(chm_store *store, const int32_t *h_pairs, int32_t n_pairs,
+                           const int64_t *h_out_offsets, int32_t *d_out, int32_t mode,
+                           void *stream);
+
+/* Launch-shape tuning of the match kernels (chosen by the autotuner; any
+ * valid value gives identical results). */
+typedef struct chm_tuning {
+  int32_t queries_per_item; /* queries per batched work item, multiple of 64, 64..8192 */
+  int32_t wg_threads;       /* 256 or 1024 */
+  int32_t lds_codes;        /* 1: stage the db image's codes in LDS when they fit */
+  int32_t grid_per_cu;      /* persistent work-groups per compute unit, 1..8 */
+} chm_tuning;
+
+chm_status chm_store_get_tuning(const chm_store *store, chm_tuning *out);
+chm_status chm_store_set_tuning(chm_store *store, const chm_tuning *tuning);
+
+/* ------------------------------------------------------------------ brute force
+ * Exhaustive matching (every db descriptor is a candidate) with the same
+ * exact squared distances and ratio test; the dense distance step runs as an
+ * int8 MFMA GEMM with int32 accumulation.  It is the exactness and roofline
+ * reference of the GPU nearest-neighbour matchers the paper compares with
+ * (Table 2, ColMap-GPU).
+ *   d_q, d_d   : device, nq x 128 and nd x 128 uint8.
+ *   d_out      : device, nq int32 (j1 or -1).
+ *   d_work     : device scratch of chm_bruteforce_work_bytes(nq, nd) bytes.
+ * nq, nd in 0..2^24-1. */
+chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t *out_bytes);
+chm_status chm_bruteforce(const uint8_t *d_q, int32_t nq, const uint8_t *d_d, int32_t nd,
+                          int32_t ratio_num, int32_t ratio_den, int32_t *d_out, void *d_work,
+                          uint64_t work_bytes, void *stream);
+
+/* ------------------------------------------------------------------ schedule
+ * Host-only MBR block schedule (Sec. 2.2 steps (1)-(5), Algorithm 1, GPS of
+ * Appendix A).  Usable without a GPU.
+ *   pairs       : host, n_pairs x 2 int32 directed pairs over images 0..n_images-1.
+ *   image_bytes : host, n_images uint64, arena bytes of each image.
+ *   cap_bytes   : residency cap (Size_gpu); every pair's two images must fit
+ *                 together (else CHM_E_CAPACITY).
+ *   blk_images  : Size_blk, images per schedule segment (>= 1).
+ * The schedule is a list of steps; step s frees `evict`, loads `load` and
+ * then matches the directed pairs `pairs` (indices into the input list); the
+ * resident set never exceeds cap_bytes and every pair appears exactly once. */
+typedef struct chm_schedule chm_schedule;
+
+chm_status chm_schedule_mbr(int32_t n_images, const int32_t *pairs, int32_t n_pairs,
+                            const uint64_t *image_bytes, uint64_t cap_bytes, int32_t blk_images,
+                            chm_schedule **out);
+int32_t chm_schedule_num_steps(const chm_schedule *s);
+/* Pointers stay valid until chm_schedule_free. */
+chm_status chm_schedule_step(const chm_schedule *s, int32_t step, const int32_t **evict,
+                             int32_t *n_evict, const int32_t **load, int32_t *n_load,
+                             const int32_t **pairs, int32_t *n_pairs);
+/* iterations, pairs handled one per step after a stalled iteration, and per
+ * iteration the matrix dimension and bandwidth (arrays of `iterations`). */
+chm_status chm_schedule_info(const chm_schedule *s, int32_t *iterations, int32_t *fallback_pairs,
+                             const int32_t **dims, const int32_t **bandwidths);
+void chm_schedule_free(chm_schedule *s);
+
+/* GPS ordering (Appendix A, Algorithm 2) of `nodes` in the undirected graph
+ * given by n_edges x 2 `edges` over ids 0..n-1; order_out receives n_nodes ids. */
+chm_status chm_gps_order(int32_t n, const int32_t *edges, int32_t n_edges, const int32_t *nodes,
+                         int32_t n_nodes, int32_t *order_out);
+
+/* Runs a schedule end to end (Algorithm 1, CascadeHashingMatching): for each
+ * step, evicts, loads the new images from host memory (h_descs[image],
+ * h_n_feats[image]; pinned memory lets the copies overlap matching on a
+ * second stream), builds their codes and tables, and matches the step's
+ * pairs in one batched launch.  Outputs as in chm_plan_create for the
+ * schedule's pair list.  The store's arena must hold cap_bytes of images. */
+chm_status chm_run_schedule(chm_store *store, const chm_schedule *s, const int32_t *h_pairs,
+                            int32_t n_pairs, const void *const *h_descs,
+                            const int32_t *h_n_feats, const int64_t *h_out_offsets,
+                            int32_t *d_out, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* CHM_H */

@@ -1,0 +1,391 @@
+"""ctypes binding of libchm.so (include/chm.h).
+
+Argument marshalling only: every step of matching runs in the library's HIP
+kernels.  Device buffers are torch CUDA tensors (ROCm), streams are torch
+streams.  The library must have been built (``build.py``); importing this
+module does not load it, the first call does and raises ``ChmError`` if the
+library is missing.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libchm.so")
+
+ABI_VERSION = 1
+PROJ_BF16, PROJ_FP32 = 0, 1
+MATCH_PLAIN, MATCH_BATCHED = 0, 1
+MAX_FEATS = 65535
+
+_STATUS = {0: "CHM_OK", -1: "CHM_E_INVALID_ARG", -2: "CHM_E_UNSUPPORTED", -3: "CHM_E_CAPACITY",
+           -4: "CHM_E_NOT_RESIDENT", -5: "CHM_E_HIP", -6: "CHM_E_INTERNAL"}
+
+
+class ChmError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("%s: %s" % (_STATUS.get(status, status), msg))
+        self.status = status
+
+
+class Config(C.Structure):
+    _fields_ = [("abi_version", C.c_uint32), ("num_tables", C.c_int32), ("bucket_bits", C.c_int32),
+                ("top_k", C.c_int32), ("ratio_num", C.c_int32), ("ratio_den", C.c_int32),
+                ("proj_precision", C.c_int32), ("reserved", C.c_int32), ("fixup_rel", C.c_double)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("h2d_bytes", C.c_uint64), ("d2d_bytes", C.c_uint64), ("resident_bytes", C.c_uint64),
+                ("resident_peak", C.c_uint64), ("fixups", C.c_uint64), ("images_loaded", C.c_int64),
+                ("images_evicted", C.c_int64), ("resident_images", C.c_int32), ("reserved", C.c_int32)]
+
+
+class Tuning(C.Structure):
+    _fields_ = [("queries_per_item", C.c_int32), ("wg_threads", C.c_int32),
+                ("lds_codes", C.c_int32), ("grid_per_cu", C.c_int32)]
+
+
+# every symbol include/chm.h declares
+EXPORTS = [
+    "chm_config_default", "chm_last_error", "chm_abi_version", "chm_image_bytes",
+    "chm_store_overhead_bytes", "chm_store_create", "chm_store_destroy", "chm_store_load",
+    "chm_store_rehash", "chm_store_evict", "chm_store_image_feats", "chm_store_stats",
+    "chm_debug_image", "chm_plan_create", "chm_plan_execute", "chm_plan_destroy",
+    "chm_match_pairs", "chm_store_get_tuning", "chm_store_set_tuning",
+    "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
+    "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
+    "chm_run_schedule",
+]
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ChmError(-6, "libchm.so is not built (run paper_2505_22089_amd/build.py)")
+        L = C.CDLL(LIB_PATH)
+        vp, i32, i64, u64 = C.c_void_p, C.c_int32, C.c_int64, C.c_uint64
+        P = C.POINTER
+        sig = {
+            "chm_config_default": (None, [P(Config)]),
+            "chm_last_error": (C.c_char_p, []),
+            "chm_abi_version": (i32, []),
+            "chm_image_bytes": (i32, [P(Config), i32, P(u64)]),
+            "chm_store_overhead_bytes": (i32, [P(Config), P(u64)]),
+            "chm_store_create": (i32, [P(Config), vp, vp, vp, u64, P(vp)]),
+            "chm_store_destroy": (None, [vp]),
+            "chm_store_load": (i32, [vp, i32, vp, vp, vp, i32, vp]),
+            "chm_store_rehash": (i32, [vp, i32, vp, vp]),
+            "chm_store_evict": (i32, [vp, i32, vp]),
+            "chm_store_image_feats": (i32, [vp, i32, P(i32)]),
+            "chm_store_stats": (i32, [vp, P(Stats)]),
+            "chm_debug_image": (i32, [vp, i32, vp, vp, vp, vp, vp, vp]),
+            "chm_plan_create": (i32, [vp, vp, i32, vp, vp, vp, i32, vp, P(vp)]),
+            "chm_plan_execute": (i32, [vp, vp]),
+            "chm_plan_destroy": (None, [vp]),
+            "chm_match_pairs": (i32, [vp, vp, i32, vp, vp, i32, vp]),
+            "chm_store_get_tuning": (i32, [vp, P(Tuning)]),
+            "chm_store_set_tuning": (i32, [vp, P(Tuning)]),
+            "chm_bruteforce_work_bytes": (i32, [i32, i32, P(u64)]),
+            "chm_bruteforce": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, u64, vp]),
+            "chm_schedule_mbr": (i32, [i32, vp, i32, vp, u64, i32, P(vp)]),
+            "chm_schedule_num_steps": (i32, [vp]),
+            "chm_schedule_step": (i32, [vp, i32, P(P(i32)), P(i32), P(P(i32)), P(i32), P(P(i32)), P(i32)]),
+            "chm_schedule_info": (i32, [vp, P(i32), P(i32), P(P(i32)), P(P(i32))]),
+            "chm_schedule_free": (None, [vp]),
+            "chm_gps_order": (i32, [i32, vp, i32, vp, i32, vp]),
+            "chm_run_schedule": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        if L.chm_abi_version() != ABI_VERSION:
+            raise ChmError(-6, "libchm ABI %d != binding %d" % (L.chm_abi_version(), ABI_VERSION))
+        _lib = L
+    return _lib
+
+
+def _check(st: int) -> None:
+    if st != 0:
+        raise ChmError(st, lib().chm_last_error().decode(errors="replace"))
+
+
+def _np_ptr(a: Optional[np.ndarray]):
+    return None if a is None else a.ctypes.data_as(C.c_void_p)
+
+
+def _dev_ptr(t) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("expected a device tensor")
+    if not t.is_contiguous():
+        raise ValueError("expected a contiguous tensor")
+    return t.data_ptr()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream()
+    return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
+
+
+def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-3) -> Config:
+    c = Config()
+    lib().chm_config_default(C.byref(c))
+    c.num_tables, c.bucket_bits, c.top_k = L, m, K
+    c.ratio_num, c.ratio_den = ratio
+    c.proj_precision = precision
+    c.fixup_rel = fixup_rel
+    return c
+
+
+def image_bytes(cfg: Config, n: int) -> int:
+    out = C.c_uint64()
+    _check(lib().chm_image_bytes(C.byref(cfg), int(n), C.byref(out)))
+    return out.value
+
+
+def store_overhead_bytes(cfg: Config) -> int:
+    out = C.c_uint64()
+    _check(lib().chm_store_overhead_bytes(C.byref(cfg), C.byref(out)))
+    return out.value
+
+
+class Store:
+    """Images resident in a caller-owned device arena (a torch uint8 tensor)."""
+
+    def __init__(self, cfg: Config, W: np.ndarray, mu: np.ndarray, arena):
+        self.cfg = cfg
+        self.arena = arena
+        W = np.ascontiguousarray(W, dtype=np.uint16)
+        mu = np.ascontiguousarray(mu, dtype=np.uint8)
+        h = C.c_void_p()
+        _check(lib().chm_store_create(C.byref(cfg), _np_ptr(W), _np_ptr(mu), _dev_ptr(arena),
+                                      arena.numel() * arena.element_size(), C.byref(h)))
+        self.handle = h
+        self.feats = {}
+        self._keep = []
+
+    def close(self):
+        if self.handle:
+            lib().chm_store_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def load(self, ids: Sequence[int], descs, stream=None):
+        """descs: device uint8 tensors (n x 128) or host numpy arrays."""
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        if len(ids) == 0:
+            return
+        on_dev = [hasattr(d, "is_cuda") and d.is_cuda for d in descs]
+        if any(on_dev) and not all(on_dev):
+            raise ValueError("descriptors must be all device tensors or all host arrays")
+        if all(on_dev):
+            ptrs = [(_dev_ptr(d) or 0) for d in descs]
+            ns = [int(d.shape[0]) for d in descs]
+            keep = None
+        else:
+            keep = [np.ascontiguousarray(d, dtype=np.uint8) for d in descs]
+            ptrs = [k.ctypes.data for k in keep]
+            ns = [k.shape[0] for k in keep]
+        parr = (C.c_void_p * len(ptrs))(*ptrs)
+        narr = np.ascontiguousarray(ns, dtype=np.int32)
+        _check(lib().chm_store_load(self.handle, len(ids), _np_ptr(ids), parr, _np_ptr(narr),
+                                    1 if all(on_dev) else 0, _stream(stream)))
+        if keep is not None:
+            # pageable host memory: the copy has been staged by the time the call returns
+            import torch
+            torch.cuda.synchronize()
+        for i, n in zip(ids, ns):
+            self.feats[int(i)] = n
+
+    def rehash(self, ids: Sequence[int], stream=None):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        _check(lib().chm_store_rehash(self.handle, len(ids), _np_ptr(ids), _stream(stream)))
+
+    def evict(self, ids: Sequence[int]):
+        ids = np.ascontiguousarray(ids, dtype=np.int32)
+        _check(lib().chm_store_evict(self.handle, len(ids), _np_ptr(ids)))
+        for i in ids:
+            self.feats.pop(int(i), None)
+
+    def image_feats(self, image_id: int) -> int:
+        out = C.c_int32()
+        _check(lib().chm_store_image_feats(self.handle, int(image_id), C.byref(out)))
+        return out.value
+
+    def stats(self) -> Stats:
+        s = Stats()
+        _check(lib().chm_store_stats(self.handle, C.byref(s)))
+        return s
+
+    def tuning(self) -> Tuning:
+        t = Tuning()
+        _check(lib().chm_store_get_tuning(self.handle, C.byref(t)))
+        return t
+
+    def set_tuning(self, queries_per_item=None, wg_threads=None, lds_codes=None, grid_per_cu=None):
+        t = self.tuning()
+        for k, v in (("queries_per_item", queries_per_item), ("wg_threads", wg_threads),
+                     ("lds_codes", lds_codes), ("grid_per_cu", grid_per_cu)):
+            if v is not None:
+                setattr(t, k, int(v))
+        _check(lib().chm_store_set_tuning(self.handle, C.byref(t)))
+
+    def debug_image(self, image_id: int, stream=None):
+        """Internal arrays of a resident image as device tensors."""
+        import torch
+        n = self.image_feats(image_id)
+        if n < 0:
+            raise ChmError(-4, "image %d is not resident" % image_id)
+        L, nb = self.cfg.num_tables, 1 << self.cfg.bucket_bits
+        dev = self.arena.device
+        codes = torch.empty((n, 4), dtype=torch.int32, device=dev)
+        ids = torch.empty((n, 8), dtype=torch.uint8, device=dev)
+        offs = torch.empty((L, nb + 1), dtype=torch.int32, device=dev)
+        mem = torch.empty((L, n), dtype=torch.int16, device=dev)
+        norms = torch.empty((n,), dtype=torch.int32, device=dev)
+        _check(lib().chm_debug_image(self.handle, int(image_id), _dev_ptr(codes), _dev_ptr(ids),
+                                     _dev_ptr(offs), _dev_ptr(mem), _dev_ptr(norms), _stream(stream)))
+        return dict(codes=codes, ids=ids, offsets=offs, members=mem, norms=norms)
+
+
+def out_offsets(store: Store, pairs: np.ndarray) -> np.ndarray:
+    pairs = np.asarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = np.zeros(len(pairs) + 1, dtype=np.int64)
+    if len(pairs):
+        offs[1:] = np.cumsum([store.feats[int(q)] for q in pairs[:, 0]])
+    return offs
+
+
+class Plan:
+    """An executable matching plan for a pair list (chm_plan_create)."""
+
+    def __init__(self, store: Store, pairs: np.ndarray, offs: np.ndarray, out, topk=None,
+                 mode: int = MATCH_BATCHED, stream=None):
+        self.store = store
+        self.pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+        self.offs = np.ascontiguousarray(offs, dtype=np.int64)
+        self.out, self.topk = out, topk
+        h = C.c_void_p()
+        _check(lib().chm_plan_create(store.handle, _np_ptr(self.pairs), len(self.pairs),
+                                     _np_ptr(self.offs), _dev_ptr(out), _dev_ptr(topk), int(mode),
+                                     _stream(stream), C.byref(h)))
+        self.handle = h
+
+    def execute(self, stream=None):
+        _check(lib().chm_plan_execute(self.handle, _stream(stream)))
+
+    def close(self):
+        if self.handle:
+            lib().chm_plan_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def match_pairs(store: Store, pairs, out, mode=MATCH_BATCHED, stream=None, offs=None):
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = out_offsets(store, pairs) if offs is None else np.ascontiguousarray(offs, np.int64)
+    _check(lib().chm_match_pairs(store.handle, _np_ptr(pairs), len(pairs), _np_ptr(offs),
+                                 _dev_ptr(out), int(mode), _stream(stream)))
+    return offs
+
+
+def bruteforce_work_bytes(nq: int, nd: int) -> int:
+    out = C.c_uint64()
+    _check(lib().chm_bruteforce_work_bytes(int(nq), int(nd), C.byref(out)))
+    return out.value
+
+
+def bruteforce(q, d, out, work, ratio=(4, 5), stream=None):
+    _check(lib().chm_bruteforce(_dev_ptr(q), int(q.shape[0]), _dev_ptr(d), int(d.shape[0]),
+                                int(ratio[0]), int(ratio[1]), _dev_ptr(out), _dev_ptr(work),
+                                work.numel() * work.element_size(), _stream(stream)))
+
+
+@dataclass
+class Schedule:
+    steps: List[dict]
+    iterations: int
+    fallback_pairs: int
+    dims: List[int]
+    bandwidths: List[int]
+    handle: Optional[C.c_void_p] = None
+
+
+def schedule_mbr(n_images: int, pairs: np.ndarray, image_bytes_: Sequence[int], cap_bytes: int,
+                 blk_images: int, keep_handle: bool = False) -> Schedule:
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    sizes = np.ascontiguousarray(image_bytes_, dtype=np.uint64)
+    h = C.c_void_p()
+    _check(lib().chm_schedule_mbr(int(n_images), _np_ptr(pairs), len(pairs), _np_ptr(sizes),
+                                  int(cap_bytes), int(blk_images), C.byref(h)))
+    L = lib()
+    steps = []
+    P32 = C.POINTER(C.c_int32)
+    for k in range(L.chm_schedule_num_steps(h)):
+        ev, ld, pp = P32(), P32(), P32()
+        nev, nld, npp = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(L.chm_schedule_step(h, k, C.byref(ev), C.byref(nev), C.byref(ld), C.byref(nld),
+                                   C.byref(pp), C.byref(npp)))
+        steps.append(dict(evict=[ev[i] for i in range(nev.value)],
+                          load=[ld[i] for i in range(nld.value)],
+                          pairs=[pp[i] for i in range(npp.value)]))
+    it, fb = C.c_int32(), C.c_int32()
+    dims, bws = P32(), P32()
+    _check(L.chm_schedule_info(h, C.byref(it), C.byref(fb), C.byref(dims), C.byref(bws)))
+    sch = Schedule(steps=steps, iterations=it.value, fallback_pairs=fb.value,
+                   dims=[dims[i] for i in range(it.value)],
+                   bandwidths=[bws[i] for i in range(it.value)])
+    if keep_handle:
+        sch.handle = h
+    else:
+        L.chm_schedule_free(h)
+    return sch
+
+
+def schedule_free(s: Schedule) -> None:
+    if s.handle:
+        lib().chm_schedule_free(s.handle)
+        s.handle = None
+
+
+def gps_order(n: int, edges: np.ndarray, nodes: Sequence[int]) -> List[int]:
+    edges = np.ascontiguousarray(edges, dtype=np.int32).reshape(-1, 2)
+    nodes = np.ascontiguousarray(nodes, dtype=np.int32)
+    out = np.zeros(len(nodes), dtype=np.int32)
+    _check(lib().chm_gps_order(int(n), _np_ptr(edges), len(edges), _np_ptr(nodes), len(nodes),
+                               _np_ptr(out)))
+    return out.tolist()
+
+
+def run_schedule(store: Store, sched: Schedule, pairs: np.ndarray, descs: Sequence[np.ndarray],
+                 offs: np.ndarray, out, stream=None) -> None:
+    """Runs a schedule kept with keep_handle=True; descs are host arrays per image."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    keep = [np.ascontiguousarray(d, dtype=np.uint8) for d in descs]
+    parr = (C.c_void_p * len(keep))(*[k.ctypes.data for k in keep])
+    ns = np.ascontiguousarray([k.shape[0] for k in keep], dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    _check(lib().chm_run_schedule(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
+                                  _np_ptr(ns), _np_ptr(offs), _dev_ptr(out), _stream(stream)))

@@ -1,0 +1,659 @@
+// Host side of libchm: the C-ABI entry points for stores, hashing and
+// matching plans.  Device memory comes only from the caller's arena.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <unordered_map>
+#include <unordered_set>
+#include <vector>
+
+#include "chm.h"
+#include "chm_internal.h"
+#include "chm_host.h"
+
+using namespace chm;
+
+static thread_local std::string g_err;
+
+chm_status chm::fail(chm_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+void chm::clear_error() { g_err.clear(); }
+
+#define HIPCHK(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      return chm::fail(CHM_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
+  } while (0)
+
+extern "C" const char* chm_last_error(void) { return g_err.c_str(); }
+extern "C" int32_t chm_abi_version(void) { return CHM_ABI_VERSION; }
+
+extern "C" void chm_config_default(chm_config* cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof *cfg);
+  cfg->abi_version = CHM_ABI_VERSION;
+  cfg->num_tables = 6;
+  cfg->bucket_bits = 8;
+  cfg->top_k = 8;
+  cfg->ratio_num = 4;
+  cfg->ratio_den = 5;
+  cfg->proj_precision = CHM_PROJ_BF16;
+  cfg->fixup_rel = 1e-3;
+}
+
+static chm_status check_config(const chm_config* c) {
+  if (!c) return fail(CHM_E_INVALID_ARG, "config is NULL");
+  if (c->abi_version != CHM_ABI_VERSION)
+    return fail(CHM_E_INVALID_ARG, "config abi_version %u != %d", c->abi_version, CHM_ABI_VERSION);
+  if (c->num_tables < 1 || c->num_tables > 8) return fail(CHM_E_INVALID_ARG, "num_tables must be 1..8");
+  if (c->bucket_bits < 0 || c->bucket_bits > 8) return fail(CHM_E_INVALID_ARG, "bucket_bits must be 0..8");
+  if (c->top_k < 1 || c->top_k > 32) return fail(CHM_E_INVALID_ARG, "top_k must be 1..32");
+  if (c->ratio_num <= 0 || c->ratio_den <= 0 || c->ratio_num > c->ratio_den || c->ratio_den > 46340)
+    return fail(CHM_E_INVALID_ARG, "ratio must satisfy 0 < num <= den <= 46340");
+  if (c->proj_precision != CHM_PROJ_BF16 && c->proj_precision != CHM_PROJ_FP32)
+    return fail(CHM_E_INVALID_ARG, "proj_precision must be CHM_PROJ_BF16 or CHM_PROJ_FP32");
+  if (c->reserved != 0) return fail(CHM_E_INVALID_ARG, "reserved must be 0");
+  if (!(c->fixup_rel >= 1e-4 && c->fixup_rel <= 0.5))
+    return fail(CHM_E_INVALID_ARG, "fixup_rel must lie in [1e-4, 0.5]");
+  return CHM_OK;
+}
+
+static inline uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+ImageLayout chm::image_layout(int L, int m, int n) {
+  ImageLayout l;
+  const uint64_t nb = 1ull << m;
+  l.n_pad = (int)round_up((uint64_t)n, 8);
+  uint64_t o = 0;
+  l.desc = o;    o += round_up((uint64_t)n * kDim, 256);
+  l.codes = o;   o += round_up((uint64_t)n * 16, 256);
+  l.ids = o;     o += round_up((uint64_t)n * 8, 256);
+  l.norms = o;   o += round_up((uint64_t)n * 4, 256);
+  l.offsets = o; o += round_up((uint64_t)L * (nb + 1) * 4, 256);
+  l.members = o; o += round_up((uint64_t)L * l.n_pad * 2, 256);
+  l.total = o;
+  return l;
+}
+
+// ------------------------------------------------------------------ arena
+
+bool Arena::alloc(uint64_t bytes, uint64_t* off) {
+  bytes = round_up(bytes ? bytes : 1, 256);
+  for (auto it = free_.begin(); it != free_.end(); ++it) {
+    if (it->second >= bytes) {
+      *off = it->first;
+      const uint64_t rest = it->second - bytes;
+      const uint64_t start = it->first + bytes;
+      free_.erase(it);
+      if (rest) free_[start] = rest;
+      return true;
+    }
+  }
+  return false;
+}
+
+void Arena::release(uint64_t off, uint64_t bytes) {
+  bytes = round_up(bytes ? bytes : 1, 256);
+  auto it = free_.emplace(off, bytes).first;
+  auto nx = std::next(it);
+  if (nx != free_.end() && it->first + it->second == nx->first) {
+    it->second += nx->second;
+    free_.erase(nx);
+  }
+  if (it != free_.begin()) {
+    auto pv = std::prev(it);
+    if (pv->first + pv->second == it->first) {
+      pv->second += it->second;
+      free_.erase(it);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ store
+
+static const uint64_t kHdrW = 0;
+static const uint64_t kHdrTau = round_up((uint64_t)kRowsPad * kDim * 2, 256);
+static const uint64_t kHdrMu = kHdrTau + round_up(kRowsPad * 4, 256);
+static const uint64_t kHdrFix = kHdrMu + 256;
+static const uint64_t kHdrBytes = kHdrFix + 256;
+
+extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
+  clear_error();
+  chm_status st = check_config(cfg);
+  if (st) return st;
+  if (!out) return fail(CHM_E_INVALID_ARG, "out is NULL");
+  *out = kHdrBytes;
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_image_bytes(const chm_config* cfg, int32_t n, uint64_t* out) {
+  clear_error();
+  chm_status st = check_config(cfg);
+  if (st) return st;
+  if (!out) return fail(CHM_E_INVALID_ARG, "out is NULL");
+  if (n < 0 || n > CHM_MAX_FEATS) return fail(CHM_E_INVALID_ARG, "n_feats must be 0..%d", CHM_MAX_FEATS);
+  *out = image_layout(cfg->num_tables, cfg->bucket_bits, n).total;
+  return CHM_OK;
+}
+
+static bool bf16_ok(uint16_t b) {
+  const int e = (b >> 7) & 0xFF;
+  if ((b & 0x7FFF) == 0) return true;  // +-0
+  if (e == 0xFF) return false;         // inf / nan
+  // magnitude in [2^-16, 32): biased exponent 111 .. 131
+  return e >= 127 - 16 && e <= 127 + 4;
+}
+
+extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_W, const uint8_t* h_mu,
+                                       void* d_arena, uint64_t arena_bytes, chm_store** out) {
+  clear_error();
+  chm_status st = check_config(cfg);
+  if (st) return st;
+  if (!h_W || !h_mu || !d_arena || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (((uintptr_t)d_arena) % 256) return fail(CHM_E_INVALID_ARG, "arena must be 256-byte aligned");
+  if (arena_bytes < kHdrBytes) return fail(CHM_E_CAPACITY, "arena smaller than the store header");
+  const int R = CHM_CODE_BITS + cfg->num_tables * cfg->bucket_bits;
+  for (int i = 0; i < R * kDim; ++i)
+    if (!bf16_ok(h_W[i]))
+      return fail(CHM_E_INVALID_ARG, "W[%d] = 0x%04x is not 0 or of magnitude in [2^-16, 32)", i, h_W[i]);
+
+  int dev = 0;
+  HIPCHK(hipGetDevice(&dev));
+  int ncu = 0;
+  HIPCHK(hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev));
+
+  std::vector<uint16_t> W(kRowsPad * kDim, 0);
+  std::memcpy(W.data(), h_W, sizeof(uint16_t) * R * kDim);
+  std::vector<float> tau(kRowsPad, 0.f);
+  for (int r = 0; r < R; ++r) {
+    double s = 0;
+    for (int d = 0; d < kDim; ++d) {
+      uint32_t u = (uint32_t)W[r * kDim + d] << 16;
+      float f;
+      std::memcpy(&f, &u, 4);
+      s += (double)f * (double)f;
+    }
+    const double t = cfg->fixup_rel * std::sqrt(s);
+    float tf = (float)t;
+    if ((double)tf < t) tf = std::nextafter(tf, INFINITY);
+    tau[r] = std::nextafter(tf, INFINITY);
+  }
+
+  chm_store* S = new chm_store();
+  S->cfg = *cfg;
+  S->R = R;
+  S->nb = 1 << cfg->bucket_bits;
+  S->base = (uint8_t*)d_arena;
+  S->size = arena_bytes;
+  S->n_cu = ncu;
+  S->device = dev;
+  S->arena.free_[kHdrBytes] = arena_bytes - kHdrBytes;
+  if (arena_bytes == kHdrBytes) S->arena.free_.clear();
+  S->dW = (uint16_t*)(S->base + kHdrW);
+  S->dTau = (float*)(S->base + kHdrTau);
+  S->dMu = S->base + kHdrMu;
+  S->dFix = (unsigned long long*)(S->base + kHdrFix);
+  std::memset(&S->stats, 0, sizeof S->stats);
+  S->tuning.queries_per_item = 1024;
+  S->tuning.wg_threads = 1024;
+  S->tuning.lds_codes = 1;
+  S->tuning.grid_per_cu = 4;
+  hipError_t e = hipMemcpy(S->dW, W.data(), W.size() * 2, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(S->dTau, tau.data(), tau.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(S->dMu, h_mu, kDim, hipMemcpyHostToDevice);
+  unsigned long long zero = 0;
+  if (e == hipSuccess) e = hipMemcpy(S->dFix, &zero, 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete S;
+    return fail(CHM_E_HIP, "store setup failed: %s", hipGetErrorString(e));
+  }
+  *out = S;
+  return CHM_OK;
+}
+
+extern "C" void chm_store_destroy(chm_store* S) {
+  if (!S) return;
+  (void)hipDeviceSynchronize();
+  if (S->cap_stream) (void)hipStreamDestroy(S->cap_stream);
+  delete S;
+}
+
+HashImage chm::hash_image_of(const chm_store* S, const ImageSlot& sl) {
+  const ImageLayout l = image_layout(S->cfg.num_tables, S->cfg.bucket_bits, sl.n);
+  uint8_t* b = S->base + sl.off;
+  HashImage h;
+  h.desc = b + l.desc;
+  h.codes = (uint4*)(b + l.codes);
+  h.ids = (uint2*)(b + l.ids);
+  h.norms = (uint32_t*)(b + l.norms);
+  h.offsets = (int32_t*)(b + l.offsets);
+  h.members = (uint16_t*)(b + l.members);
+  h.n = sl.n;
+  h.n_pad = l.n_pad;
+  return h;
+}
+
+chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& slots, hipStream_t s) {
+  ProjConsts pc;
+  pc.W = S->dW;
+  pc.tau = S->dTau;
+  pc.mu = S->dMu;
+  pc.fixups = S->dFix;
+  pc.R = S->R;
+  for (size_t i0 = 0; i0 < slots.size(); i0 += kHashBatch) {
+    HashBatch hb;
+    std::memset(&hb, 0, sizeof hb);
+    hb.L = S->cfg.num_tables;
+    hb.m = S->cfg.bucket_bits;
+    int cnt = 0, tiles = 0;
+    for (size_t i = i0; i < slots.size() && cnt < kHashBatch; ++i, ++cnt) {
+      hb.img[cnt] = hash_image_of(S, *slots[i]);
+      hb.tile_prefix[cnt] = tiles;
+      tiles += (slots[i]->n + 31) / 32;
+    }
+    hb.tile_prefix[cnt] = tiles;
+    for (int k = cnt + 1; k <= kHashBatch; ++k) hb.tile_prefix[k] = tiles;
+    hb.count = cnt;
+    HIPCHK(launch_project(hb, pc, S->cfg.proj_precision == CHM_PROJ_FP32, S->n_cu, s));
+    HIPCHK(launch_buckets(hb, s));
+  }
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_load(chm_store* S, int32_t count, const int32_t* ids,
+                                     const void* const* descs, const int32_t* n_feats,
+                                     int32_t on_device, void* stream) {
+  clear_error();
+  if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
+  if (count < 0) return fail(CHM_E_INVALID_ARG, "count < 0");
+  if (count == 0) return CHM_OK;
+  if (!ids || !descs || !n_feats) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  std::unordered_set<int32_t> seen;
+  for (int i = 0; i < count; ++i) {
+    if (ids[i] < 0) return fail(CHM_E_INVALID_ARG, "image id %d < 0", ids[i]);
+    if (S->images.count(ids[i])) return fail(CHM_E_INVALID_ARG, "image %d already resident", ids[i]);
+    if (!seen.insert(ids[i]).second) return fail(CHM_E_INVALID_ARG, "image %d listed twice", ids[i]);
+    if (n_feats[i] < 0 || n_feats[i] > CHM_MAX_FEATS)
+      return fail(CHM_E_INVALID_ARG, "image %d: n_feats %d outside 0..%d", ids[i], n_feats[i], CHM_MAX_FEATS);
+    if (n_feats[i] > 0 && !descs[i]) return fail(CHM_E_INVALID_ARG, "image %d: descriptors NULL", ids[i]);
+  }
+  std::vector<ImageSlot> slots(count);
+  for (int i = 0; i < count; ++i) {
+    const ImageLayout l = image_layout(S->cfg.num_tables, S->cfg.bucket_bits, n_feats[i]);
+    slots[i].n = n_feats[i];
+    slots[i].bytes = l.total;
+    if (!S->arena.alloc(l.total, &slots[i].off)) {
+      for (int k = 0; k < i; ++k) S->arena.release(slots[k].off, slots[k].bytes);
+      return fail(CHM_E_CAPACITY, "arena cannot hold image %d (%llu bytes)", ids[i],
+                  (unsigned long long)l.total);
+    }
+  }
+  hipStream_t s = (hipStream_t)stream;
+  const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  std::vector<const ImageSlot*> ptrs;
+  for (int i = 0; i < count; ++i) {
+    if (slots[i].n > 0) {
+      hipError_t e = hipMemcpyAsync(S->base + slots[i].off, descs[i], (size_t)slots[i].n * kDim, kind, s);
+      if (e != hipSuccess) {
+        for (int k = 0; k < count; ++k) S->arena.release(slots[k].off, slots[k].bytes);
+        return fail(CHM_E_HIP, "descriptor copy failed: %s", hipGetErrorString(e));
+      }
+    }
+    slots[i].gen = ++S->gen_counter;
+    auto& ref = S->images[ids[i]] = slots[i];
+    ptrs.push_back(&ref);
+    S->stats.resident_bytes += slots[i].bytes;
+    (on_device ? S->stats.d2d_bytes : S->stats.h2d_bytes) += (uint64_t)slots[i].n * kDim;
+    S->stats.images_loaded += 1;
+  }
+  S->stats.resident_images = (int32_t)S->images.size();
+  S->stats.resident_peak = std::max(S->stats.resident_peak, S->stats.resident_bytes);
+  return hash_images(S, ptrs, s);
+}
+
+extern "C" chm_status chm_store_rehash(chm_store* S, int32_t count, const int32_t* ids, void* stream) {
+  clear_error();
+  if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
+  if (count < 0 || (count > 0 && !ids)) return fail(CHM_E_INVALID_ARG, "bad image list");
+  std::vector<const ImageSlot*> ptrs;
+  for (int i = 0; i < count; ++i) {
+    auto it = S->images.find(ids[i]);
+    if (it == S->images.end()) return fail(CHM_E_NOT_RESIDENT, "image %d is not resident", ids[i]);
+    ptrs.push_back(&it->second);
+  }
+  return hash_images(S, ptrs, (hipStream_t)stream);
+}
+
+extern "C" chm_status chm_store_evict(chm_store* S, int32_t count, const int32_t* ids) {
+  clear_error();
+  if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
+  if (count < 0 || (count > 0 && !ids)) return fail(CHM_E_INVALID_ARG, "bad image list");
+  for (int i = 0; i < count; ++i)
+    if (!S->images.count(ids[i])) return fail(CHM_E_NOT_RESIDENT, "image %d is not resident", ids[i]);
+  for (int i = 0; i < count; ++i) {
+    auto it = S->images.find(ids[i]);
+    if (it == S->images.end()) continue;  // listed twice
+    S->arena.release(it->second.off, it->second.bytes);
+    S->stats.resident_bytes -= it->second.bytes;
+    S->stats.images_evicted += 1;
+    S->images.erase(it);
+  }
+  S->stats.resident_images = (int32_t)S->images.size();
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_image_feats(const chm_store* S, int32_t id, int32_t* out) {
+  clear_error();
+  if (!S || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  auto it = S->images.find(id);
+  *out = it == S->images.end() ? -1 : it->second.n;
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_stats(chm_store* S, chm_stats* out) {
+  clear_error();
+  if (!S || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  unsigned long long f = 0;
+  HIPCHK(hipDeviceSynchronize());
+  HIPCHK(hipMemcpy(&f, S->dFix, 8, hipMemcpyDeviceToHost));
+  S->stats.fixups = f;
+  *out = S->stats;
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_debug_image(chm_store* S, int32_t id, uint32_t* d_codes, uint8_t* d_ids,
+                                      int32_t* d_offsets, uint16_t* d_members, uint32_t* d_norms,
+                                      void* stream) {
+  clear_error();
+  if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
+  auto it = S->images.find(id);
+  if (it == S->images.end()) return fail(CHM_E_NOT_RESIDENT, "image %d is not resident", id);
+  const HashImage h = hash_image_of(S, it->second);
+  hipStream_t s = (hipStream_t)stream;
+  const int L = S->cfg.num_tables;
+  const size_t n = (size_t)h.n;
+  if (d_codes && n) HIPCHK(hipMemcpyAsync(d_codes, h.codes, n * 16, hipMemcpyDeviceToDevice, s));
+  if (d_ids && n) HIPCHK(hipMemcpyAsync(d_ids, h.ids, n * 8, hipMemcpyDeviceToDevice, s));
+  if (d_norms && n) HIPCHK(hipMemcpyAsync(d_norms, h.norms, n * 4, hipMemcpyDeviceToDevice, s));
+  if (d_offsets)
+    HIPCHK(hipMemcpyAsync(d_offsets, h.offsets, (size_t)L * (S->nb + 1) * 4, hipMemcpyDeviceToDevice, s));
+  if (d_members && n)
+    HIPCHK(hipMemcpy2DAsync(d_members, n * 2, h.members, (size_t)h.n_pad * 2, n * 2, L,
+                            hipMemcpyDeviceToDevice, s));
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_get_tuning(const chm_store* S, chm_tuning* out) {
+  clear_error();
+  if (!S || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  *out = S->tuning;
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_set_tuning(chm_store* S, const chm_tuning* t) {
+  clear_error();
+  if (!S || !t) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (t->queries_per_item < 64 || t->queries_per_item > 8192 || t->queries_per_item % 64)
+    return fail(CHM_E_INVALID_ARG, "queries_per_item must be a multiple of 64 in 64..8192");
+  if (t->wg_threads != 256 && t->wg_threads != 1024)
+    return fail(CHM_E_INVALID_ARG, "wg_threads must be 256 or 1024");
+  if (t->lds_codes != 0 && t->lds_codes != 1) return fail(CHM_E_INVALID_ARG, "lds_codes must be 0 or 1");
+  if (t->grid_per_cu < 1 || t->grid_per_cu > 8) return fail(CHM_E_INVALID_ARG, "grid_per_cu must be 1..8");
+  S->tuning = *t;
+  return CHM_OK;
+}
+
+// ------------------------------------------------------------------ plans
+
+static const int kLdsBudget = 160 * 1024 - 1024;
+
+int chm::lds_max_feats(const chm_store* S) {
+  const size_t off = (size_t)S->cfg.num_tables * (S->nb + 1) * 4;
+  return (int)((kLdsBudget - (int)off) / 16);
+}
+
+static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
+  const HashImage h = hash_image_of(S, sl);
+  ImageDev d;
+  d.desc = h.desc;
+  d.codes = h.codes;
+  d.ids = h.ids;
+  d.norms = h.norms;
+  d.offsets = h.offsets;
+  d.members = h.members;
+  d.n = h.n;
+  d.n_pad = h.n_pad;
+  return d;
+}
+
+chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
+                           int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream,
+                           chm_plan** out) {
+  if (mode != CHM_MATCH_PLAIN && mode != CHM_MATCH_BATCHED) return fail(CHM_E_INVALID_ARG, "bad mode");
+  std::vector<PairDev> pd(P);
+  std::unordered_map<int32_t, uint64_t> gens;
+  int64_t total_out = 0;
+  for (int p = 0; p < P; ++p) {
+    auto iq = S->images.find(h_pairs[2 * p]);
+    auto id = S->images.find(h_pairs[2 * p + 1]);
+    if (iq == S->images.end() || id == S->images.end())
+      return fail(CHM_E_NOT_RESIDENT, "pair %d names an image that is not resident", p);
+    if (starts[p] < 0) return fail(CHM_E_INVALID_ARG, "negative output offset");
+    pd[p].q = image_dev(S, iq->second);
+    pd[p].d = image_dev(S, id->second);
+    pd[p].out_off = starts[p];
+    total_out += iq->second.n;
+    gens[iq->first] = iq->second.gen;
+    gens[id->first] = id->second.gen;
+  }
+  if (total_out > 0 && !d_out) return fail(CHM_E_INVALID_ARG, "d_out is NULL");
+
+  chm_plan* pl = new chm_plan();
+  pl->st = S;
+  pl->mode = mode;
+  pl->n_pairs = P;
+  pl->out = d_out;
+  pl->topk = d_topk;
+  pl->gens.assign(gens.begin(), gens.end());
+  pl->tun = S->tuning;
+  const int ldsmax = pl->tun.lds_codes ? lds_max_feats(S) : 0;
+  pl->lds_max = ldsmax;
+
+  std::vector<WorkItem> items;
+  if (mode == CHM_MATCH_PLAIN) {
+    const int qp = pl->tun.wg_threads;
+    pl->pair_begin.resize(P);
+    pl->pair_count.resize(P);
+    pl->pair_lds.resize(P);
+    for (int p = 0; p < P; ++p) {
+      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+      pl->pair_begin[p] = (int)items.size();
+      for (int q0 = 0; q0 < pd[p].q.n; q0 += qp)
+        items.push_back({p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0});
+      pl->pair_count[p] = (int)items.size() - pl->pair_begin[p];
+      pl->pair_lds[p] = lds;
+    }
+  } else {
+    const int qpi = pl->tun.queries_per_item;
+    std::vector<std::pair<double, WorkItem>> a, b;
+    for (int p = 0; p < P; ++p) {
+      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+      for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
+        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
+        const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
+        (lds ? a : b).push_back({cost, w});
+      }
+    }
+    auto byc = [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
+      if (x.first != y.first) return x.first > y.first;
+      if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
+      return x.second.q0 < y.second.q0;
+    };
+    std::sort(a.begin(), a.end(), byc);
+    std::sort(b.begin(), b.end(), byc);
+    for (auto& x : a) items.push_back(x.second);
+    for (auto& x : b) items.push_back(x.second);
+    pl->n_lds_items = (int)a.size();
+  }
+  pl->n_items = (int)items.size();
+
+  const uint64_t pairs_bytes = round_up(sizeof(PairDev) * (size_t)std::max(P, 1), 256);
+  const uint64_t items_bytes = round_up(sizeof(WorkItem) * (size_t)std::max(pl->n_items, 1), 256);
+  pl->mem_bytes = pairs_bytes + items_bytes + 256;
+  if (!S->arena.alloc(pl->mem_bytes, &pl->mem_off)) {
+    delete pl;
+    return fail(CHM_E_CAPACITY, "arena cannot hold the plan's work list (%llu bytes)",
+                (unsigned long long)(pairs_bytes + items_bytes + 256));
+  }
+  pl->dPairs = (PairDev*)(S->base + pl->mem_off);
+  pl->dItems = (WorkItem*)(S->base + pl->mem_off + pairs_bytes);
+  pl->dQueue = (uint32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes);
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipSuccess;
+  if (P) e = hipMemcpyAsync(pl->dPairs, pd.data(), sizeof(PairDev) * P, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && pl->n_items)
+    e = hipMemcpyAsync(pl->dItems, items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) {
+    S->arena.release(pl->mem_off, pl->mem_bytes);
+    delete pl;
+    return fail(CHM_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
+  }
+
+  MatchArgs& a = pl->args;
+  a.pairs = pl->dPairs;
+  a.items = pl->dItems;
+  a.n_items = 0;
+  a.item_base = 0;
+  a.queue = pl->dQueue;
+  a.out = d_out;
+  a.topk = d_topk;
+  a.L = S->cfg.num_tables;
+  a.nb = S->nb;
+  a.K = S->cfg.top_k;
+  a.ratio_num = S->cfg.ratio_num;
+  a.ratio_den = S->cfg.ratio_den;
+  a.lds_max_feats = ldsmax;
+
+  if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {
+    hipStream_t cs = S->cap_stream;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, 2, cs);
+    const int nl = pl->n_lds_items, ng = pl->n_items - pl->n_lds_items;
+    if (e == hipSuccess && nl > 0) {
+      MatchArgs x = a;
+      x.items = pl->dItems;
+      x.n_items = nl;
+      x.queue = pl->dQueue;
+      const int grid = std::min(nl, S->n_cu * (pl->tun.wg_threads == 1024 ? 1 : 1));
+      e = launch_match(x, a.K, pl->tun.wg_threads, true, true, grid, cs);
+    }
+    if (e == hipSuccess && ng > 0) {
+      MatchArgs x = a;
+      x.items = pl->dItems + nl;
+      x.n_items = ng;
+      x.queue = pl->dQueue + 1;
+      x.lds_max_feats = 0;
+      const int grid = std::min(ng, S->n_cu * pl->tun.grid_per_cu);
+      e = launch_match(x, a.K, 256, false, true, grid, cs);
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(cs, &g);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    if (e != hipSuccess) {
+      S->arena.release(pl->mem_off, pl->mem_bytes);
+      delete pl;
+      return fail(CHM_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+    }
+  }
+  *out = pl;
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_plan_create(chm_store* S, const int32_t* h_pairs, int32_t P,
+                                      const int64_t* h_offs, int32_t* d_out, uint32_t* d_topk,
+                                      int32_t mode, void* stream, chm_plan** out) {
+  clear_error();
+  if (!S || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (P < 0 || (P > 0 && (!h_pairs || !h_offs))) return fail(CHM_E_INVALID_ARG, "bad pair list");
+  for (int p = 0; p < P; ++p) {
+    auto iq = S->images.find(h_pairs[2 * p]);
+    if (iq == S->images.end() || !S->images.count(h_pairs[2 * p + 1]))
+      return fail(CHM_E_NOT_RESIDENT, "pair %d names an image that is not resident", p);
+    if (h_offs[p + 1] - h_offs[p] != iq->second.n)
+      return fail(CHM_E_INVALID_ARG, "pair %d: output range %lld != query features %d", p,
+                  (long long)(h_offs[p + 1] - h_offs[p]), iq->second.n);
+  }
+  return plan_build(S, h_pairs, P, h_offs, d_out, d_topk, mode, stream, out);
+}
+
+static bool plan_fresh(const chm_plan* pl) {
+  for (auto& g : pl->gens) {
+    auto it = pl->st->images.find(g.first);
+    if (it == pl->st->images.end() || it->second.gen != g.second) return false;
+  }
+  return true;
+}
+
+extern "C" chm_status chm_plan_execute(chm_plan* pl, void* stream) {
+  clear_error();
+  if (!pl) return fail(CHM_E_INVALID_ARG, "plan is NULL");
+  if (!plan_fresh(pl)) return fail(CHM_E_NOT_RESIDENT, "an image of the plan was evicted or reloaded");
+  hipStream_t s = (hipStream_t)stream;
+  pl->last_stream = s;
+  pl->executed = true;
+  if (pl->n_items == 0) return CHM_OK;
+  if (pl->mode == CHM_MATCH_BATCHED) {
+    HIPCHK(hipGraphLaunch(pl->exec, s));
+    return CHM_OK;
+  }
+  for (int p = 0; p < pl->n_pairs; ++p) {
+    if (pl->pair_count[p] == 0) continue;
+    MatchArgs x = pl->args;
+    x.n_items = pl->n_items;
+    x.item_base = pl->pair_begin[p];
+    if (!pl->pair_lds[p]) x.lds_max_feats = 0;
+    HIPCHK(launch_match(x, x.K, pl->tun.wg_threads, pl->pair_lds[p] != 0, false, pl->pair_count[p], s));
+  }
+  return CHM_OK;
+}
+
+extern "C" void chm_plan_destroy(chm_plan* pl) {
+  if (!pl) return;
+  if (pl->executed) (void)hipStreamSynchronize(pl->last_stream);
+  if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
+  pl->st->arena.release(pl->mem_off, pl->mem_bytes);
+  delete pl;
+}
+
+extern "C" chm_status chm_match_pairs(chm_store* S, const int32_t* h_pairs, int32_t P,
+                                      const int64_t* h_offs, int32_t* d_out, int32_t mode,
+                                      void* stream) {
+  chm_plan* pl = nullptr;
+  chm_status st = chm_plan_create(S, h_pairs, P, h_offs, d_out, nullptr, mode, stream, &pl);
+  if (st) return st;
+  st = chm_plan_execute(pl, stream);
+  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  chm_plan_destroy(pl);
+  if (st) return st;
+  if (e != hipSuccess) return fail(CHM_E_HIP, "matching failed: %s", hipGetErrorString(e));
+  return CHM_OK;
+}

@@ -1,0 +1,90 @@
+// Host-side internals of libchm (store, arena, plans).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <map>
+#include <unordered_map>
+#include <utility>
+#include <vector>
+
+#include "chm.h"
+#include "chm_internal.h"
+
+namespace chm {
+
+chm_status fail(chm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+void clear_error();
+
+// First-fit sub-allocator over [0, size) of the caller's arena, 256-byte granules.
+struct Arena {
+  std::map<uint64_t, uint64_t> free_;  // offset -> bytes
+  bool alloc(uint64_t bytes, uint64_t* off);
+  void release(uint64_t off, uint64_t bytes);
+};
+
+struct ImageLayout {
+  uint64_t desc, codes, ids, norms, offsets, members, total;
+  int n_pad;
+};
+ImageLayout image_layout(int L, int m, int n);
+
+struct ImageSlot {
+  uint64_t off = 0;
+  uint64_t bytes = 0;
+  int32_t n = 0;
+  uint64_t gen = 0;
+};
+
+}  // namespace chm
+
+struct chm_store {
+  chm_config cfg;
+  int R = 0;
+  int nb = 0;
+  uint8_t* base = nullptr;
+  uint64_t size = 0;
+  chm::Arena arena;
+  uint16_t* dW = nullptr;
+  float* dTau = nullptr;
+  uint8_t* dMu = nullptr;
+  unsigned long long* dFix = nullptr;
+  std::unordered_map<int32_t, chm::ImageSlot> images;
+  uint64_t gen_counter = 0;
+  chm_stats stats;
+  chm_tuning tuning;
+  int n_cu = 0;
+  int device = 0;
+  hipStream_t cap_stream = nullptr;
+};
+
+struct chm_plan {
+  chm_store* st = nullptr;
+  int mode = 0;
+  int n_pairs = 0;
+  int n_items = 0;
+  int n_lds_items = 0;
+  int lds_max = 0;
+  int32_t* out = nullptr;
+  uint32_t* topk = nullptr;
+  std::vector<std::pair<int32_t, uint64_t>> gens;
+  uint64_t mem_off = 0, mem_bytes = 0;
+  chm::PairDev* dPairs = nullptr;
+  chm::WorkItem* dItems = nullptr;
+  uint32_t* dQueue = nullptr;
+  std::vector<int> pair_begin, pair_count;
+  std::vector<char> pair_lds;
+  chm::MatchArgs args;
+  chm_tuning tun;
+  hipGraphExec_t exec = nullptr;
+  hipStream_t last_stream = nullptr;
+  bool executed = false;
+};
+
+namespace chm {
+HashImage hash_image_of(const chm_store* S, const ImageSlot& sl);
+chm_status hash_images(chm_store* S, const std::vector<const ImageSlot*>& slots, hipStream_t s);
+int lds_max_feats(const chm_store* S);
+chm_status plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
+                      int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream, chm_plan** out);
+}  // namespace chm

@@ -26,3 +26,11 @@ def orc():
     from oracle import oracle
     oracle.lib()
     return oracle
+
+
+@pytest.fixture(autouse=True)
+def _announce(request):
+    """Name each GPU test on stdout before it touches the device."""
+    if request.node.get_closest_marker("gpu") is not None:
+        print("\n[gpu-test] %s" % request.node.nodeid, flush=True)
+    yield

@@ -1,0 +1,186 @@
+"""GPU parity of the HIP path with the CPU oracle, through the C-ABI.
+
+Integer work (codes, bucket ids, tables, top-K keys, match indices) must be
+bit-identical.  Hashing is checked before any match kernel reads the tables.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2505_22089_amd import chm, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from tests.gpu_helpers import gpu_arrays, load_all, new_store, run_match  # noqa: E402
+
+
+def small_workload(sizes, seed=0, L=6, m=8, K=8, copies=0.5):
+    rng = np.random.default_rng(seed)
+    base = synth.sift_like(rng, max(sizes) if sizes else 1)
+    imgs = []
+    for n in sizes:
+        k = int(copies * n)
+        x = np.concatenate([synth.noisy_copy(rng, base[:k]), synth.sift_like(rng, n - k)])
+        imgs.append(x[rng.permutation(n)] if n else x)
+    W = synth.projection_weights(42, 128 + L * m)
+    wl = synth.Workload(name="small", images=imgs, pairs=np.zeros((0, 2), np.int32), W=W,
+                        mu=synth.centring_vector(imgs), L=L, m=m, K=K)
+    return wl
+
+
+def check_hash(store, wl, ids):
+    for i in ids:
+        g = gpu_arrays(store, i)
+        ref = O.hash_image(wl.images[i], wl.W[:128 + store.cfg.num_tables * store.cfg.bucket_bits],
+                           wl.mu, store.cfg.num_tables, store.cfg.bucket_bits)
+        assert np.array_equal(g["codes"], ref.codes), "codes of image %d" % i
+        assert np.array_equal(g["ids"], ref.ids), "bucket ids of image %d" % i
+        assert np.array_equal(g["offsets"], ref.offsets), "offsets of image %d" % i
+        assert np.array_equal(g["members"], ref.members), "members of image %d" % i
+        x = wl.images[i].astype(np.int64)
+        assert np.array_equal(g["norms"].astype(np.int64), (x * x).sum(1))
+
+
+@pytest.mark.parametrize("precision", [chm.PROJ_BF16, chm.PROJ_FP32])
+def test_hash_parity_config1(precision):
+    wl = synth.config1()
+    st = new_store(wl, precision)
+    load_all(st, wl.images)
+    check_hash(st, wl, [0, 1])
+    assert st.stats().fixups > 0
+
+
+@pytest.mark.parametrize("sizes", [[0, 1, 2, 31, 32, 33], [63, 64, 65, 1000], [4097, 129]])
+def test_hash_parity_ragged(sizes):
+    wl = small_workload(sizes, seed=len(sizes))
+    st = new_store(wl)
+    load_all(st, wl.images)
+    check_hash(st, wl, range(len(sizes)))
+
+
+@pytest.mark.parametrize("L,m", [(1, 0), (3, 5), (8, 8), (6, 1)])
+def test_hash_parity_table_shapes(L, m):
+    wl = small_workload([700, 300], seed=L * 10 + m, L=L, m=m)
+    st = new_store(wl)
+    load_all(st, wl.images)
+    check_hash(st, wl, [0, 1])
+
+
+def near_hyperplane(wl, n, rng):
+    """Descriptors whose projections on some rows are as close to 0 as integer
+    steps allow (|p| far below the fp32 accumulation error bound)."""
+    Wf = (wl.W.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+    out = []
+    for k in range(n):
+        x = synth.sift_like(rng, 1)[0].astype(np.int64)
+        r = int(rng.integers(0, Wf.shape[0]))
+        for _ in range(40):
+            p = float(Wf[r] @ (x - wl.mu.astype(np.int64)))
+            if abs(p) < 1e-6:
+                break
+            d = int(np.argmax(np.abs(Wf[r]) * ((x > 0) & (x < 255))))
+            step = -int(np.sign(p) * np.sign(Wf[r, d]))
+            if abs(Wf[r, d]) > 2 * abs(p):
+                # a unit step overshoots; try the smallest useful coefficient instead
+                cand = np.nonzero((np.abs(Wf[r]) <= 2 * abs(p)) & (np.abs(Wf[r]) > 0) &
+                                  (x > 0) & (x < 255))[0]
+                if len(cand) == 0:
+                    break
+                d = int(cand[np.argmax(np.abs(Wf[r, cand]))])
+                step = -int(np.sign(p) * np.sign(Wf[r, d]))
+            x[d] = np.clip(x[d] + step, 0, 255)
+        out.append(x.astype(np.uint8))
+    return np.stack(out)
+
+
+def test_hash_parity_near_hyperplane_descriptors():
+    rng = np.random.default_rng(77)
+    wl = small_workload([10], seed=5)
+    X = near_hyperplane(wl, 256, rng)
+    wl.images = [X, np.stack([wl.mu] * 3)]
+    for prec in (chm.PROJ_BF16, chm.PROJ_FP32):
+        st = new_store(wl, prec)
+        load_all(st, wl.images)
+        check_hash(st, wl, [0, 1])
+        st.close()
+
+
+def check_matches(st, wl, pairs, mode, K):
+    out, topk, offs = run_match(st, pairs, mode, want_topk=True)
+    H = {}
+    for p, (q, d) in enumerate(pairs):
+        for i in (q, d):
+            if i not in H:
+                H[i] = O.hash_image(wl.images[i], wl.W[:128 + st.cfg.num_tables * st.cfg.bucket_bits],
+                                    wl.mu, st.cfg.num_tables, st.cfg.bucket_bits)
+        ro, rt, _ = O.match_pair(H[q], H[d], st.cfg.num_tables, st.cfg.bucket_bits, K,
+                                 wl.ratio, want_topk=True)
+        a, b = offs[p], offs[p + 1]
+        assert np.array_equal(topk[a:b], rt), "top-K keys of pair %d (%d -> %d)" % (p, q, d)
+        assert np.array_equal(out[a:b], ro), "matches of pair %d (%d -> %d)" % (p, q, d)
+    return out
+
+
+@pytest.mark.parametrize("mode", [chm.MATCH_PLAIN, chm.MATCH_BATCHED])
+def test_match_parity_config1(mode):
+    wl = synth.config1()
+    st = new_store(wl)
+    load_all(st, wl.images)
+    out = check_matches(st, wl, [(0, 1), (1, 0), (0, 0)], mode, 2)
+    gt = {int(a): int(b) for a, b in wl.gt}
+    assert np.mean([out[a] == b for a, b in gt.items()]) > 0.9
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 8, 16, 32])
+def test_match_parity_k(K):
+    wl = small_workload([900, 700, 0, 1], seed=K)
+    st = new_store(wl, K=K)
+    load_all(st, wl.images)
+    pairs = [(0, 1), (1, 0), (1, 1), (0, 2), (2, 0), (3, 0), (0, 3)]
+    check_matches(st, wl, pairs, chm.MATCH_BATCHED, K)
+    check_matches(st, wl, pairs, chm.MATCH_PLAIN, K)
+
+
+@pytest.mark.parametrize("L,m", [(1, 0), (3, 5), (8, 8)])
+def test_match_parity_table_shapes(L, m):
+    wl = small_workload([600, 500], seed=3 + L, L=L, m=m)
+    st = new_store(wl, K=8)
+    load_all(st, wl.images)
+    check_matches(st, wl, [(0, 1), (1, 0)], chm.MATCH_BATCHED, 8)
+
+
+def test_match_parity_lds_and_global_paths():
+    # one db image above the LDS stage capacity, others below; ragged query counts
+    wl = small_workload([12000, 3001, 65, 8000], seed=9, copies=0.3)
+    st = new_store(wl, K=8)
+    load_all(st, wl.images)
+    pairs = [(1, 0), (2, 0), (0, 1), (3, 1), (1, 3), (2, 3)]
+    ref = check_matches(st, wl, pairs, chm.MATCH_BATCHED, 8)
+    for tun in (dict(lds_codes=0), dict(wg_threads=256), dict(queries_per_item=64),
+                dict(queries_per_item=4096, grid_per_cu=1)):
+        st.set_tuning(**tun)
+        for mode in (chm.MATCH_BATCHED, chm.MATCH_PLAIN):
+            out, _, _ = run_match(st, pairs, mode)
+            assert np.array_equal(out, ref), "tuning %s mode %d" % (tun, mode)
+
+
+def test_match_duplicates_and_degenerate():
+    rng = np.random.default_rng(1)
+    wl = small_workload([50], seed=1)
+    same = np.repeat(synth.sift_like(rng, 1), 40, axis=0)
+    wl.images = [same, np.concatenate([same[:5], synth.sift_like(rng, 30)]), np.stack([wl.mu] * 4)]
+    wl.mu = synth.centring_vector(wl.images)
+    st = new_store(wl, K=8)
+    load_all(st, wl.images)
+    check_matches(st, wl, [(0, 1), (1, 0), (0, 0), (2, 2), (2, 1), (1, 2)], chm.MATCH_BATCHED, 8)
+
+
+def test_batched_replay_is_deterministic():
+    wl = small_workload([2000, 2500, 1500], seed=4)
+    st = new_store(wl, K=8)
+    load_all(st, wl.images)
+    pairs = [(0, 1), (1, 2), (2, 0), (1, 0)]
+    a, _, _ = run_match(st, pairs, chm.MATCH_BATCHED, repeats=3)
+    b, _, _ = run_match(st, pairs, chm.MATCH_PLAIN)
+    assert np.array_equal(a, b)
