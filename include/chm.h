@@ -153,8 +153,8 @@ chm_status chm_store_stats(chm_store *store, chm_stats *out);
 
 /* Copies an image's internal arrays to caller device buffers (for tests):
  *   d_codes   : n x 4 uint32 (bit r of the long code in word r/32, bit r%32)
- *   d_ids     : n x 8 uint8 (byte t = bucket id of table t, bit j of it from
- *               projection row 128 + m*t + j; bytes >= L are 0)
+ *   d_ids     : L x n uint8, table-major: bucket id of each descriptor in
+ *               table t, bit j of it from projection row 128 + m*t + j
  *   d_offsets : L x (2^m + 1) int32, bucket b of table t holds
  *               members[t][offsets[t][b] .. offsets[t][b+1])
  *   d_members : L x n uint16 db indices, ascending inside each bucket

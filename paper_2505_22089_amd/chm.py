@@ -256,7 +256,7 @@ class Store:
         L, nb = self.cfg.num_tables, 1 << self.cfg.bucket_bits
         dev = self.arena.device
         codes = torch.empty((n, 4), dtype=torch.int32, device=dev)
-        ids = torch.empty((n, 8), dtype=torch.uint8, device=dev)
+        ids = torch.empty((L, n), dtype=torch.uint8, device=dev)
         offs = torch.empty((L, nb + 1), dtype=torch.int32, device=dev)
         mem = torch.empty((L, n), dtype=torch.int16, device=dev)
         norms = torch.empty((n,), dtype=torch.int32, device=dev)

@@ -1,23 +1,34 @@
 // Lookup tables of Sec. 2.3.1 step (1): for every image and table, the 2^m
 // buckets as a stable counting sort of the bucket ids (CSR: offsets +
-// members, members ascending inside each bucket).  One work-group per
-// (image, table); the stable scatter ranks equal ids inside a wavefront with
-// ballots and across wavefronts with per-wave counts in LDS.
+// members, members ascending inside each bucket).
+//
+// One work-group per (image, table).  The table's ids are staged in LDS once;
+// each wavefront owns a contiguous segment of descriptors.  Pass 1 counts
+// per (wavefront, bucket); a scan turns the counts into each wavefront's
+// starting position inside each bucket; pass 2 scatters, ranking equal ids
+// inside a 64-lane chunk with ballots (lanes agreeing on every id bit), so
+// the order inside a bucket is the descriptor order.
 #include "chm_internal.h"
 
 namespace chm {
 
-constexpr int kBucketWG = 256;
+constexpr int kBucketWG = 512;
 constexpr int kBucketWaves = kBucketWG / 64;
+constexpr int kBucketMaxN = 65536;
 
-__device__ __forceinline__ uint32_t id_byte(uint2 v, int t) {
-  return ((t < 4 ? v.x >> (8 * t) : v.y >> (8 * (t - 4)))) & 0xFFu;
+__device__ __forceinline__ uint64_t peers_of(uint32_t b, bool valid, int m) {
+  uint64_t peers = __ballot(valid);
+  for (int bit = 0; bit < m; ++bit) {
+    const bool set = (b >> bit) & 1u;
+    const uint64_t bm = __ballot(valid && set);
+    peers &= set ? bm : ~bm;
+  }
+  return peers;
 }
 
 __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
-  __shared__ uint32_t hist[256];
-  __shared__ uint32_t base[256];
-  __shared__ uint32_t wcnt[kBucketWaves][256];
+  __shared__ uint8_t sId[kBucketMaxN];
+  __shared__ uint32_t cnt[kBucketWaves][256];
 
   const int im = blockIdx.x / hb.L;
   const int t = blockIdx.x % hb.L;
@@ -27,53 +38,79 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   const int tid = threadIdx.x;
   const int wave = tid >> 6;
   const int lane = __lane_id();
+  const uint8_t* ids = I.ids + (size_t)t * I.n_pad;
 
-  hist[tid] = 0;
+  // stage ids (n_pad is a multiple of 8 and the table start is 8-byte aligned)
+  for (int i = tid; i < I.n_pad / 8; i += kBucketWG)
+    reinterpret_cast<uint2*>(sId)[i] = reinterpret_cast<const uint2*>(ids)[i];
+  for (int i = tid; i < kBucketWaves * 256; i += kBucketWG) (&cnt[0][0])[i] = 0;
   __syncthreads();
-  for (int i = tid; i < n; i += kBucketWG) atomicAdd(&hist[id_byte(I.ids[i], t)], 1u);
+
+  // each wavefront: a contiguous segment of whole 64-lane chunks
+  const int chunks = (n + 63) / 64;
+  const int per = (chunks + kBucketWaves - 1) / kBucketWaves;
+  const int c0 = wave * per, c1 = min(chunks, c0 + per);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+
+  for (int c = c0; c < c1; ++c) {
+    const int i = c * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t b = valid ? sId[i] : 0u;
+    const uint64_t peers = peers_of(b, valid, hb.m);
+    if (valid && (peers & lt) == 0) cnt[wave][b] += (uint32_t)__popcll(peers);
+  }
   __syncthreads();
-  if (tid == 0) {
-    uint32_t run = 0;
-    for (int b = 0; b < nb; ++b) {
-      base[b] = run;
-      I.offsets[t * (nb + 1) + b] = (int32_t)run;
-      run += hist[b];
+
+  // offsets of the table, and each wavefront's start inside each bucket
+  if (tid < 64) {
+    // scan over buckets: lane handles buckets 4*lane .. 4*lane+3
+    uint32_t tot[4], run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 4 * lane + k;
+      uint32_t s = 0;
+      if (b < nb)
+        for (int w = 0; w < kBucketWaves; ++w) s += cnt[w][b];
+      tot[k] = s;
+      run += s;
     }
-    I.offsets[t * (nb + 1) + nb] = (int32_t)run;
+    uint32_t incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    uint32_t base = incl - run;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 4 * lane + k;
+      if (b < nb) {
+        I.offsets[t * (nb + 1) + b] = (int32_t)base;
+        uint32_t pos = base;
+        for (int w = 0; w < kBucketWaves; ++w) {
+          const uint32_t c = cnt[w][b];
+          cnt[w][b] = pos;
+          pos += c;
+        }
+      }
+      base += tot[k];
+    }
+    if (lane == 63) I.offsets[t * (nb + 1) + nb] = (int32_t)incl;
   }
   __syncthreads();
 
   uint16_t* mem = I.members + (size_t)t * I.n_pad;
-  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  for (int c = 0; c < n; c += kBucketWG) {
-    const int i = c + tid;
+  for (int c = c0; c < c1; ++c) {
+    const int i = c * 64 + lane;
     const bool valid = i < n;
-    const uint32_t b = valid ? id_byte(I.ids[i], t) : 0u;
-#pragma unroll
-    for (int w = 0; w < kBucketWaves; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
-    uint64_t peers = __ballot(valid);
-    for (int bit = 0; bit < hb.m; ++bit) {
-      const bool set = (b >> bit) & 1u;
-      const uint64_t bm = __ballot(valid && set);
-      peers &= set ? bm : ~bm;
-    }
+    const uint32_t b = valid ? sId[i] : 0u;
+    const uint64_t peers = peers_of(b, valid, hb.m);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
-    if (valid && rank == 0) wcnt[wave][b] = (uint32_t)__popcll(peers);
-    __syncthreads();
-    if (valid) {
-      uint32_t pos = base[b] + rank;
-      for (int w = 0; w < wave; ++w) pos += wcnt[w][b];
-      mem[pos] = (uint16_t)i;
-    }
-    __syncthreads();
-    if (tid < nb) {
-      uint32_t add = 0;
-#pragma unroll
-      for (int w = 0; w < kBucketWaves; ++w) add += wcnt[w][tid];
-      base[tid] += add;
-    }
-    __syncthreads();
+    const uint32_t start = valid ? cnt[wave][b] : 0u;
+    if (valid) mem[start + rank] = (uint16_t)i;
+    __builtin_amdgcn_wave_barrier();
+    if (valid && rank == 0) cnt[wave][b] = start + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
   }
   for (int i = n + tid; i < I.n_pad; i += kBucketWG) mem[i] = 0;
 }

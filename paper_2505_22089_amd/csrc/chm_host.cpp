@@ -82,7 +82,7 @@ ImageLayout chm::image_layout(int L, int m, int n) {
   uint64_t o = 0;
   l.desc = o;    o += round_up((uint64_t)n * kDim, 256);
   l.codes = o;   o += round_up((uint64_t)n * 16, 256);
-  l.ids = o;     o += round_up((uint64_t)n * 8, 256);
+  l.ids = o;     o += round_up((uint64_t)L * l.n_pad, 256);
   l.norms = o;   o += round_up((uint64_t)n * 4, 256);
   l.offsets = o; o += round_up((uint64_t)L * (nb + 1) * 4, 256);
   l.members = o; o += round_up((uint64_t)L * l.n_pad * 2, 256);
@@ -128,9 +128,11 @@ void Arena::release(uint64_t off, uint64_t bytes) {
 
 static const uint64_t kHdrW = 0;
 static const uint64_t kHdrTau = round_up((uint64_t)kRowsPad * kDim * 2, 256);
-static const uint64_t kHdrMu = kHdrTau + round_up(kRowsPad * 4, 256);
+static const uint64_t kHdrCmu = kHdrTau + round_up(kRowsPad * 4, 256);
+static const uint64_t kHdrMu = kHdrCmu + round_up(kRowsPad * 8, 256);
 static const uint64_t kHdrFix = kHdrMu + 256;
-static const uint64_t kHdrBytes = kHdrFix + 256;
+static const uint64_t kHdrFixList = kHdrFix + 256;
+static const uint64_t kHdrBytes = kHdrFixList + round_up(((uint64_t)kFixListCap + 2) * 4, 256);
 
 extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
   clear_error();
@@ -180,14 +182,17 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   std::vector<uint16_t> W(kRowsPad * kDim, 0);
   std::memcpy(W.data(), h_W, sizeof(uint16_t) * R * kDim);
   std::vector<float> tau(kRowsPad, 0.f);
+  std::vector<double> cmu(kRowsPad, 0.0);
   for (int r = 0; r < R; ++r) {
-    double s = 0;
+    double s = 0, c = 0;
     for (int d = 0; d < kDim; ++d) {
       uint32_t u = (uint32_t)W[r * kDim + d] << 16;
       float f;
       std::memcpy(&f, &u, 4);
       s += (double)f * (double)f;
+      c += (double)f * (double)h_mu[d];  // exact: multiples of 2^-23 below 2^21
     }
+    cmu[r] = c;
     const double t = cfg->fixup_rel * std::sqrt(s);
     float tf = (float)t;
     if ((double)tf < t) tf = std::nextafter(tf, INFINITY);
@@ -206,8 +211,10 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   if (arena_bytes == kHdrBytes) S->arena.free_.clear();
   S->dW = (uint16_t*)(S->base + kHdrW);
   S->dTau = (float*)(S->base + kHdrTau);
+  S->dCmu = (double*)(S->base + kHdrCmu);
   S->dMu = S->base + kHdrMu;
   S->dFix = (unsigned long long*)(S->base + kHdrFix);
+  S->dFixList = (uint32_t*)(S->base + kHdrFixList);
   std::memset(&S->stats, 0, sizeof S->stats);
   S->tuning.queries_per_item = 1024;
   S->tuning.wg_threads = 1024;
@@ -215,6 +222,7 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   S->tuning.grid_per_cu = 4;
   hipError_t e = hipMemcpy(S->dW, W.data(), W.size() * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dTau, tau.data(), tau.size() * 4, hipMemcpyHostToDevice);
+  if (e == hipSuccess) e = hipMemcpy(S->dCmu, cmu.data(), cmu.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dMu, h_mu, kDim, hipMemcpyHostToDevice);
   unsigned long long zero = 0;
   if (e == hipSuccess) e = hipMemcpy(S->dFix, &zero, 8, hipMemcpyHostToDevice);
@@ -240,7 +248,7 @@ HashImage chm::hash_image_of(const chm_store* S, const ImageSlot& sl) {
   HashImage h;
   h.desc = b + l.desc;
   h.codes = (uint4*)(b + l.codes);
-  h.ids = (uint2*)(b + l.ids);
+  h.ids = b + l.ids;
   h.norms = (uint32_t*)(b + l.norms);
   h.offsets = (int32_t*)(b + l.offsets);
   h.members = (uint16_t*)(b + l.members);
@@ -253,25 +261,32 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
   ProjConsts pc;
   pc.W = S->dW;
   pc.tau = S->dTau;
+  pc.cmu = S->dCmu;
   pc.mu = S->dMu;
   pc.fixups = S->dFix;
+  pc.fixlist = S->dFixList;
+  pc.fix_cap = kFixListCap;
   pc.R = S->R;
-  for (size_t i0 = 0; i0 < slots.size(); i0 += kHashBatch) {
+  for (size_t i0 = 0; i0 < slots.size();) {
     HashBatch hb;
     std::memset(&hb, 0, sizeof hb);
     hb.L = S->cfg.num_tables;
     hb.m = S->cfg.bucket_bits;
     int cnt = 0, tiles = 0;
+    int descs = 0;
     for (size_t i = i0; i < slots.size() && cnt < kHashBatch; ++i, ++cnt) {
+      if (cnt > 0 && descs + slots[i]->n > kHashBatchDescs) break;
       hb.img[cnt] = hash_image_of(S, *slots[i]);
       hb.tile_prefix[cnt] = tiles;
       tiles += (slots[i]->n + 31) / 32;
+      descs += slots[i]->n;
     }
     hb.tile_prefix[cnt] = tiles;
     for (int k = cnt + 1; k <= kHashBatch; ++k) hb.tile_prefix[k] = tiles;
     hb.count = cnt;
     HIPCHK(launch_project(hb, pc, S->cfg.proj_precision == CHM_PROJ_FP32, S->n_cu, s));
     HIPCHK(launch_buckets(hb, s));
+    i0 += cnt;
   }
   return CHM_OK;
 }
@@ -389,7 +404,8 @@ extern "C" chm_status chm_debug_image(chm_store* S, int32_t id, uint32_t* d_code
   const int L = S->cfg.num_tables;
   const size_t n = (size_t)h.n;
   if (d_codes && n) HIPCHK(hipMemcpyAsync(d_codes, h.codes, n * 16, hipMemcpyDeviceToDevice, s));
-  if (d_ids && n) HIPCHK(hipMemcpyAsync(d_ids, h.ids, n * 8, hipMemcpyDeviceToDevice, s));
+  if (d_ids && n)
+    HIPCHK(hipMemcpy2DAsync(d_ids, n, h.ids, (size_t)h.n_pad, n, L, hipMemcpyDeviceToDevice, s));
   if (d_norms && n) HIPCHK(hipMemcpyAsync(d_norms, h.norms, n * 4, hipMemcpyDeviceToDevice, s));
   if (d_offsets)
     HIPCHK(hipMemcpyAsync(d_offsets, h.offsets, (size_t)L * (S->nb + 1) * 4, hipMemcpyDeviceToDevice, s));

@@ -47,8 +47,10 @@ struct chm_store {
   chm::Arena arena;
   uint16_t* dW = nullptr;
   float* dTau = nullptr;
+  double* dCmu = nullptr;
   uint8_t* dMu = nullptr;
   unsigned long long* dFix = nullptr;
+  uint32_t* dFixList = nullptr;
   std::unordered_map<int32_t, chm::ImageSlot> images;
   uint64_t gen_counter = 0;
   chm_stats stats;

@@ -16,7 +16,7 @@ constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 struct ImageDev {
   const uint8_t* desc;      // n x 128
   const uint4* codes;       // n: long code, bit r in word r/32 at r%32
-  const uint2* ids;         // n: byte t = bucket id of table t
+  const uint8_t* ids;       // L x n_pad: bucket id of each descriptor, table-major
   const uint32_t* norms;    // n: squared L2 norm
   const int32_t* offsets;   // L x (nb + 1)
   const uint16_t* members;  // L x n_pad, ascending inside each bucket
@@ -54,12 +54,12 @@ struct MatchArgs {
 };
 
 // Hashing of a batch of images, passed by value.
-constexpr int kHashBatch = 24;
+constexpr int kHashBatch = 64;
 
 struct HashImage {
   const uint8_t* desc;
   uint4* codes;
-  uint2* ids;
+  uint8_t* ids;             // L x n_pad, table-major
   uint32_t* norms;
   int32_t* offsets;
   uint16_t* members;
@@ -78,10 +78,18 @@ struct HashBatch {
 struct ProjConsts {
   const uint16_t* W;        // kRowsPad x 128 bf16 bits (rows >= R are zero)
   const float* tau;         // kRowsPad: fixup_rel * ||W_r|| (rounded up), 0 for padding
+  const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
   unsigned long long* fixups;  // running count of fp64 recomputes
+  uint32_t* fixlist;        // [0] count, [1] overflow flag, [2..] entries (im<<24 | r<<16 | d)
+  uint32_t fix_cap;         // entries the list holds
   int32_t R;                // 128 + L*m
 };
+
+// Fix-up list capacity and the per-batch descriptor budget that keeps the
+// expected list (about 1.6 entries per descriptor) well inside it.
+constexpr uint32_t kFixListCap = 1u << 22;
+constexpr int kHashBatchDescs = 1 << 20;
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, int n_cu,

@@ -8,6 +8,7 @@
 
 #include "chm.h"
 #include "chm_host.h"
+#include "chm_internal.h"
 
 using namespace chm;
 
@@ -62,12 +63,29 @@ extern "C" chm_status chm_run_schedule(chm_store* S, const chm_schedule* sc, con
 
 extern "C" chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t* out) {
   clear_error();
-  if (!out || nq < 0 || nd < 0) return fail(CHM_E_INVALID_ARG, "bad arguments");
-  *out = 256;
+  if (!out || nq < 0 || nd < 0 || nq >= (1 << 24) || nd >= (1 << 24))
+    return fail(CHM_E_INVALID_ARG, "bad arguments");
+  const uint64_t b = (uint64_t)bruteforce_splits(nq, nd) * (uint64_t)nq * 16u;
+  *out = b < 256 ? 256 : b;
   return CHM_OK;
 }
 
-extern "C" chm_status chm_bruteforce(const uint8_t*, int32_t, const uint8_t*, int32_t, int32_t,
-                                     int32_t, int32_t*, void*, uint64_t, void*) {
-  return fail(CHM_E_UNSUPPORTED, "brute force not built yet");
+extern "C" chm_status chm_bruteforce(const uint8_t* d_q, int32_t nq, const uint8_t* d_d, int32_t nd,
+                                     int32_t ra, int32_t rb, int32_t* d_out, void* d_work,
+                                     uint64_t work_bytes, void* stream) {
+  clear_error();
+  uint64_t need = 0;
+  chm_status st = chm_bruteforce_work_bytes(nq, nd, &need);
+  if (st) return st;
+  if (ra <= 0 || rb <= 0 || ra > rb || rb > 46340)
+    return fail(CHM_E_INVALID_ARG, "ratio must satisfy 0 < num <= den <= 46340");
+  if (nq > 0 && (!d_q || !d_out || !d_work)) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (nd > 0 && !d_d) return fail(CHM_E_INVALID_ARG, "NULL db descriptors");
+  if (work_bytes < need) return fail(CHM_E_CAPACITY, "workspace needs %llu bytes", (unsigned long long)need);
+  if (((uintptr_t)d_q | (uintptr_t)d_d | (uintptr_t)d_work) % 16)
+    return fail(CHM_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  hipError_t e = launch_bruteforce(d_q, nq, d_d, nd, ra, rb, d_out, d_work, bruteforce_splits(nq, nd),
+                                   (hipStream_t)stream);
+  if (e != hipSuccess) return fail(CHM_E_HIP, "brute force launch failed: %s", hipGetErrorString(e));
+  return CHM_OK;
 }

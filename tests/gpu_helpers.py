@@ -34,7 +34,7 @@ def gpu_arrays(store, image_id):
     torch.cuda.synchronize()
     L = store.cfg.num_tables
     return dict(codes=d["codes"].cpu().numpy().view(np.uint32),
-                ids=d["ids"].cpu().numpy()[:, :L],
+                ids=np.ascontiguousarray(d["ids"].cpu().numpy().T),
                 offsets=d["offsets"].cpu().numpy(),
                 members=d["members"].cpu().numpy().view(np.uint16).astype(np.int32),
                 norms=d["norms"].cpu().numpy().view(np.uint32))

@@ -184,3 +184,15 @@ def test_batched_replay_is_deterministic():
     a, _, _ = run_match(st, pairs, chm.MATCH_BATCHED, repeats=3)
     b, _, _ = run_match(st, pairs, chm.MATCH_PLAIN)
     assert np.array_equal(a, b)
+
+
+def test_hash_parity_when_fixup_list_overflows():
+    """fixup_rel = 0.5 marks most projections borderline: the per-tile list
+    overflows and the batch is rebuilt from exact values; bits still match."""
+    wl = small_workload([300, 77], seed=21)
+    for prec in (chm.PROJ_BF16, chm.PROJ_FP32):
+        st = new_store(wl, prec, fixup_rel=0.5)
+        load_all(st, wl.images)
+        check_hash(st, wl, [0, 1])
+        assert st.stats().fixups >= 377 * 176
+        st.close()

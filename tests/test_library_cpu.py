@@ -46,7 +46,7 @@ def test_config_defaults_and_validation():
     assert c.abi_version == chm.ABI_VERSION and chm.lib().chm_abi_version() == 1
     assert chm.image_bytes(c, 0) > 0
     b8000 = chm.image_bytes(c, 8000)
-    assert b8000 >= 8000 * (128 + 16 + 8 + 4 + 12)
+    assert b8000 >= 8000 * (128 + 16 + 6 + 4 + 12)   # desc, code, L ids, norm, L u16 members
     for bad in (dict(L=0), dict(L=9), dict(m=9), dict(K=0), dict(K=33), dict(ratio=(5, 4)),
                 dict(ratio=(0, 5)), dict(fixup_rel=1e-9), dict(precision=7)):
         with pytest.raises(chm.ChmError) as e:
