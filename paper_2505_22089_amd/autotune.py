@@ -1,0 +1,110 @@
+"""Autotuner for the batched match launch.
+
+Chooses chm_tuning (queries per work item, work-group size, LDS staging of
+the db codes, persistent work-groups per compute unit) for a store and a
+pair list by timing the batched plan for each candidate on the device.  Any
+tuning gives identical results: every candidate's output is compared with
+the first one's and a mismatch raises.  Winners are cached in a JSON file
+keyed by the device name and the workload shape, so later runs skip the
+search.
+"""
+from __future__ import annotations
+
+import json
+import os
+import time
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import chm
+
+CANDIDATES: List[Dict[str, int]] = [
+    dict(queries_per_item=1024, wg_threads=1024, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=2048, wg_threads=1024, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=4096, wg_threads=1024, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=512, wg_threads=1024, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=1024, wg_threads=256, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=256, wg_threads=256, lds_codes=0, grid_per_cu=4),
+    dict(queries_per_item=1024, wg_threads=256, lds_codes=0, grid_per_cu=8),
+]
+
+DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chm_autotune.json")
+
+
+def _bucket(v: float) -> int:
+    return int(round(np.log2(max(1.0, float(v))) * 2))
+
+
+def shape_key(store: "chm.Store", pairs: np.ndarray) -> str:
+    import torch
+    dev = torch.cuda.get_device_name(0)
+    nq = np.array([store.feats[int(q)] for q in pairs[:, 0]], dtype=np.float64)
+    nd = np.array([store.feats[int(d)] for d in pairs[:, 1]], dtype=np.float64)
+    c = store.cfg
+    return "%s|L%d m%d K%d|P%d|q%d|d%d|dmax%d" % (
+        dev, c.num_tables, c.bucket_bits, c.top_k, _bucket(len(pairs)), _bucket(nq.mean() if len(nq) else 1),
+        _bucket(nd.mean() if len(nd) else 1), _bucket(nd.max() if len(nd) else 1))
+
+
+def _time_plan(store, pairs, offs, out, reps: int) -> float:
+    import torch
+    plan = chm.Plan(store, pairs, offs, out, None, chm.MATCH_BATCHED)
+    try:
+        plan.execute()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            plan.execute()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps
+    finally:
+        plan.close()
+
+
+def tune(store: "chm.Store", pairs: np.ndarray, reps: int = 5, cache: Optional[str] = DEFAULT_CACHE,
+         candidates: Optional[List[Dict[str, int]]] = None, verbose: bool = False) -> Dict[str, int]:
+    """Picks and applies the fastest tuning for this store and pair list."""
+    import torch
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    key = shape_key(store, pairs)
+    table = {}
+    if cache and os.path.exists(cache):
+        try:
+            table = json.load(open(cache))
+        except (OSError, ValueError):
+            table = {}
+    if key in table:
+        best = table[key]["tuning"]
+        store.set_tuning(**best)
+        return best
+    offs = chm.out_offsets(store, pairs)
+    total = max(1, int(offs[-1]))
+    ref = None
+    results = []
+    for cand in (candidates or CANDIDATES):
+        store.set_tuning(**cand)
+        out = torch.empty(total, dtype=torch.int32, device=store.arena.device)
+        t = _time_plan(store, pairs, offs, out, reps)
+        o = out.cpu().numpy()
+        if ref is None:
+            ref = o
+        elif not np.array_equal(o, ref):
+            raise RuntimeError("tuning %s changed the matches" % cand)
+        results.append((t, cand))
+        if verbose:
+            print("autotune %s: %.3f ms" % (cand, t * 1e3), flush=True)
+    results.sort(key=lambda x: x[0])
+    best = results[0][1]
+    store.set_tuning(**best)
+    if cache:
+        table[key] = {"tuning": best, "ms": results[0][0] * 1e3,
+                      "tried": [{"tuning": c, "ms": t * 1e3} for t, c in results]}
+        try:
+            os.makedirs(os.path.dirname(cache), exist_ok=True)
+            tmp = cache + ".tmp"
+            json.dump(table, open(tmp, "w"), indent=1)
+            os.replace(tmp, cache)
+        except OSError:
+            pass
+    return best

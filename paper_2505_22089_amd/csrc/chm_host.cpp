@@ -132,7 +132,7 @@ static const uint64_t kHdrCmu = kHdrTau + round_up(kRowsPad * 4, 256);
 static const uint64_t kHdrMu = kHdrCmu + round_up(kRowsPad * 8, 256);
 static const uint64_t kHdrFix = kHdrMu + 256;
 static const uint64_t kHdrFixList = kHdrFix + 256;
-static const uint64_t kHdrBytes = kHdrFixList + round_up(((uint64_t)kFixListCap + 2) * 4, 256);
+static const uint64_t kHdrBytes = kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + kMaxProjWaves) * 4, 256);
 
 extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
   clear_error();

@@ -81,14 +81,17 @@ struct ProjConsts {
   const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
   unsigned long long* fixups;  // running count of fp64 recomputes
-  uint32_t* fixlist;        // [0] count, [1] overflow flag, [2..] entries (im<<24 | r<<16 | d)
+  uint32_t* fixlist;        // [0] overflow flag, [1..n_waves] per-wave counts, then
+                            // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d)
   uint32_t fix_cap;         // entries the list holds
+  int32_t n_waves;          // projection wavefronts of the launch (set by launch_project)
   int32_t R;                // 128 + L*m
 };
 
 // Fix-up list capacity and the per-batch descriptor budget that keeps the
 // expected list (about 1.6 entries per descriptor) well inside it.
 constexpr uint32_t kFixListCap = 1u << 22;
+constexpr int kMaxProjWaves = 8192;
 constexpr int kHashBatchDescs = 1 << 20;
 
 // Host-side launchers (defined in the .hip files).

@@ -34,6 +34,20 @@ typedef __attribute__((address_space(1))) const uint32_t gcu32;
 typedef __attribute__((address_space(1))) const uint8_t gcu8;
 typedef __attribute__((address_space(1))) const int32_t gci32;
 
+// popcount(x) + acc in one instruction
+__device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
+  uint32_t r;
+  asm("v_bcnt_u32_b32 %0, %1, %2" : "=v"(r) : "v"(x), "v"(acc));
+  return r;
+}
+
+// 2 * m + (bit of this lane in `lanes`): appends one pass bit per instruction
+__device__ __forceinline__ uint32_t shift_in(uint32_t m, uint64_t lanes) {
+  uint32_t r;
+  asm("v_addc_co_u32 %0, vcc, %1, %1, %2" : "=v"(r) : "v"(m), "s"(lanes) : "vcc");
+  return r;
+}
+
 __device__ __forceinline__ uint32_t med3u(uint32_t a, uint32_t b, uint32_t c) {
   uint32_t r;
   asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
@@ -109,23 +123,25 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
     // (key below the current KT-th key).  Only passing slots are inserted,
     // lane by lane, so the insertion cost follows each lane's own passes.
     uint32_t key[8];
-    uint32_t pmask = 0;
+    uint32_t pmask = 0;  // slot k at bit 7 - k
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
       const uint32_t j = (k & 1) ? (w[k >> 1] >> 16) : (w[k >> 1] & 0xFFFFu);
       const uint4 c = code_of<LDSC>(sCodes, P.d.codes, j);
-      uint32_t h = 0;
-      h = __builtin_popcount(qc.x ^ c.x) + h;
-      h = __builtin_popcount(qc.y ^ c.y) + h;
-      h = __builtin_popcount(qc.z ^ c.z) + h;
-      h = __builtin_popcount(qc.w ^ c.w) + h;
+      const uint32_t h =
+          bcnt_acc(qc.w ^ c.w, bcnt_acc(qc.z ^ c.z, bcnt_acc(qc.y ^ c.y, bcnt_acc(qc.x ^ c.x, 0u))));
       key[k] = (h << 24) | j;
-      const bool pass = ((uint32_t)(base + k) < (uint32_t)len) & (key[k] < thr);
-      pmask |= pass ? (1u << k) : 0u;
+      pmask = shift_in(pmask, __ballot(key[k] < thr));
+    }
+    // slots outside [s, e): k < -base or k >= len - base
+    {
+      const int lo = max(0, -base), hi = min(8, len - base);
+      const uint32_t valid = (0xFFu >> lo) & ~(0xFFu >> hi);
+      pmask &= valid;
     }
     while (pmask) {
-      const uint32_t i = __builtin_ctz(pmask);
-      pmask &= pmask - 1u;
+      const uint32_t i = 7u - (31u - __builtin_clz(pmask));
+      pmask &= ~(0x80u >> i);
       const uint32_t s01 = (i & 1) ? key[1] : key[0], s23 = (i & 1) ? key[3] : key[2];
       const uint32_t s45 = (i & 1) ? key[5] : key[4], s67 = (i & 1) ? key[7] : key[6];
       const uint32_t s03 = (i & 2) ? s23 : s01, s47 = (i & 2) ? s67 : s45;

@@ -14,11 +14,13 @@
 // k_project: one work-group of kProjWaves wavefronts shares W in LDS; each
 // wavefront loops over 32-descriptor tiles.  The 192 (padded) rows are done
 // in two passes of three 32x32 output blocks.  Codes and bucket ids are
-// written from the fp32 signs; borderline (descriptor, row) entries go to a
-// per-wave LDS list and, once per tile, to the global fix-up list.
-// k_fixup: a persistent grid over the list; each lane recomputes one entry
-// exactly and patches its bit with a 32-bit atomic.  If any list overflowed
-// (adversarial inputs only), it recomputes every projection of the batch.
+// written from the fp32 signs; each wavefront writes the borderline
+// (descriptor, row) entries of its tiles into its own region of the global
+// fix-up list, without atomics.
+// k_fixup: wavefronts walk the regions; each lane recomputes one entry
+// exactly in fp64 and patches its bit with a 32-bit atomic.  If a region
+// overflowed (adversarial inputs only), k_fixup_all instead rebuilds every
+// code and bucket id of the batch from exact values.
 #include "chm_internal.h"
 
 namespace chm {
@@ -32,7 +34,6 @@ typedef __attribute__((address_space(1))) const u32x4 gcu32x4;
 
 constexpr int kProjWaves = 8;
 constexpr int kProjWG = 64 * kProjWaves;
-constexpr int kTileFixCap = 1024;  // per-wave LDS list for one tile
 
 __device__ __forceinline__ uint32_t bf16_bits_of_int(int v) {
   // |v| <= 255 has at most 8 significant bits: the bf16 pattern is the upper
@@ -53,7 +54,6 @@ __device__ __forceinline__ void wave_sync() {
 template <bool FP32>
 __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc) {
   __shared__ uint16_t sW[kRowsPad * kWStride];
-  __shared__ uint32_t sFix[kProjWaves][kTileFixCap];
   __shared__ uint32_t sWords[kProjWaves][32 * 6];
   __shared__ float sTau[kRowsPad];
   __shared__ float sSd[kProjWaves][32];   // ||x - mu|| of the wave's tile rows
@@ -74,12 +74,17 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
   const int lane = __lane_id();
   const int half = lane >> 5;
   const int col = lane & 31;
-  uint32_t* fix = sFix[wave];
   uint32_t* words = sWords[wave];
   // Lane L < 32 collects the words of descriptor L: it is accumulator element
   // e = 4*(L/8) + L%4, in the upper ballot half iff (L/4) is odd.
   const int eL = 4 * ((lane >> 3) & 3) + (lane & 3);
   const bool hiL = (lane >> 2) & 1;
+
+  // this wavefront's region of the fix-up list: [gw * cap_w, (gw + 1) * cap_w)
+  const uint32_t gw = blockIdx.x * kProjWaves + wave;
+  const uint32_t cap_w = pc.fix_cap / pc.n_waves;
+  uint32_t* region = pc.fixlist + 1 + pc.n_waves + (size_t)gw * cap_w;
+  uint32_t wcount = 0;
 
   const int total_tiles = hb.tile_prefix[hb.count];
   int im = 0;  // tiles of a wavefront increase, so the image search resumes
@@ -129,8 +134,8 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
     if (lane < 32) sSd[wave][lane] = valid ? sqrtf((float)nc) * 1.000001f : 0.f;
     wave_sync();
 
-    int nfix = 0;
-    float4 sd4;
+    // per lane, borderline accumulator elements: bit 16*(blk&1) + e of bm3[blk>>1]
+    uint32_t bm3[3] = {0u, 0u, 0u};
 #pragma unroll
     for (int pass = 0; pass < 2; ++pass) {
       f32x16 acc[3];
@@ -182,28 +187,48 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
         const float tau = sTau[32 * blk + col];
         uint32_t word = 0;
 #pragma unroll
-        for (int e = 0; e < 16; ++e) {
-          if ((e & 3) == 0) sd4 = *reinterpret_cast<const float4*>(&sSd[wave][8 * (e >> 2) + 4 * half]);
-          const float sde = (e & 3) == 0 ? sd4.x : (e & 3) == 1 ? sd4.y : (e & 3) == 2 ? sd4.z : sd4.w;
-          const float v = acc[b][e];
-          const uint64_t bits = __ballot(v > 0.f);
-          if (e == eL) word = hiL ? (uint32_t)(bits >> 32) : (uint32_t)bits;
-          const bool border = fabsf(v) < tau * sde;
-          const uint64_t bm = __ballot(border);
-          if (bm) {
-            if (border) {
-              const uint32_t below = __builtin_amdgcn_mbcnt_hi(
-                  (uint32_t)(bm >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u));
-              const uint32_t idx = (uint32_t)nfix + below;
-              const int drel = 8 * (e >> 2) + 4 * half + (e & 3);
-              if (idx < kTileFixCap)
-                fix[idx] = ((uint32_t)im << 24) | ((uint32_t)(32 * blk + col) << 16) | (uint32_t)(d0 + drel);
-            }
-            nfix += __popcll(bm);
+        for (int q = 0; q < 4; ++q) {
+          // descriptors 8q + 4*half + 0..3 of the tile
+          const float4 sd4 = *reinterpret_cast<const float4*>(&sSd[wave][8 * q + 4 * half]);
+          const float th[4] = {tau * sd4.x, tau * sd4.y, tau * sd4.z, tau * sd4.w};
+#pragma unroll
+          for (int i = 0; i < 4; ++i) {
+            const int e = 4 * q + i;
+            const float v = acc[b][e];
+            const uint64_t bits = __ballot(v > 0.f);
+            if (e == eL) word = hiL ? (uint32_t)(bits >> 32) : (uint32_t)bits;
+            bm3[blk >> 1] |= (fabsf(v) < th[i]) ? (1u << (16 * (blk & 1) + e)) : 0u;
           }
         }
         if (lane < 32) words[lane * 6 + blk] = word;
       }
+    }
+    // Borderline entries of the tile go straight to this wavefront's region of
+    // the global list (no atomics): lane offsets from a wave prefix sum.
+    {
+      const int mine = __popc(bm3[0]) + __popc(bm3[1]) + __popc(bm3[2]);
+      int incl = mine;
+#pragma unroll
+      for (int d = 1; d < 64; d <<= 1) {
+        const int v = __shfl_up(incl, d);
+        if (lane >= d) incl += v;
+      }
+      const uint32_t tile_n = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
+      uint32_t idx = wcount + (uint32_t)(incl - mine);
+#pragma unroll
+      for (int w3 = 0; w3 < 3; ++w3) {
+        uint32_t m = bm3[w3];
+        while (m) {
+          const int bit = __builtin_ctz(m);
+          m &= m - 1u;
+          const int blk = 2 * w3 + (bit >> 4), e = bit & 15;
+          const int drel = 8 * (e >> 2) + 4 * half + (e & 3);
+          if (idx < cap_w)
+            region[idx] = ((uint32_t)im << 24) | ((uint32_t)(32 * blk + col) << 16) | (uint32_t)(d0 + drel);
+          ++idx;
+        }
+      }
+      wcount += tile_n;
     }
     wave_sync();
     if (lane < 32 && valid) {
@@ -215,23 +240,11 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
         I.ids[(size_t)t * I.n_pad + dr] = (uint8_t)((uint32_t)(bb >> (hb.m * t)) & mask);
       I.norms[dr] = nx;
     }
-    if (nfix > 0) {
-      // hand the tile's entries to the global list (one atomic per tile)
-      uint32_t base = 0;
-      if (lane == 0) {
-        if (nfix > kTileFixCap) {
-          atomicOr(pc.fixlist + 1, 1u);
-        } else {
-          base = atomicAdd(pc.fixlist, (uint32_t)nfix);
-          if (base + (uint32_t)nfix > pc.fix_cap) atomicOr(pc.fixlist + 1, 1u);
-        }
-      }
-      base = __shfl(base, 0);
-      if (nfix <= kTileFixCap)
-        for (int i = lane; i < nfix; i += 64)
-          if (base + (uint32_t)i < pc.fix_cap) pc.fixlist[2 + base + i] = fix[i];
-    }
     wave_sync();
+  }
+  if (lane == 0) {
+    pc.fixlist[1 + gw] = wcount;
+    if (wcount > cap_w) atomicOr(pc.fixlist, 1u);
   }
 }
 
@@ -264,32 +277,69 @@ __device__ __forceinline__ void set_bit(uint32_t* word, uint32_t bit, bool on) {
   else atomicAnd(word, ~bit);
 }
 
-__global__ __launch_bounds__(256) void k_fixup(HashBatch hb, ProjConsts pc) {
-  if (pc.fixlist[1] != 0) return;  // overflow: k_fixup_all rebuilds the batch
-  const uint32_t count = pc.fixlist[0];
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gsize = gridDim.x * blockDim.x;
-  for (uint32_t i = gtid; i < count; i += gsize) {
-    const uint32_t ent = pc.fixlist[2 + i];
-    const int im = ent >> 24, r = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
-    const HashImage& I = hb.img[im];
-    const double p = exact_projection(I.desc + (size_t)d * kDim, pc.W + r * kDim, pc.cmu[r]);
-    if (r < 128) {
-      set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (r >> 5), 1u << (r & 31), p > 0.0);
-    } else {
-      const int t = (r - 128) / hb.m, j = (r - 128) % hb.m;
-      const size_t byte = (size_t)t * I.n_pad + d;
-      uint32_t* w = reinterpret_cast<uint32_t*>(I.ids + (byte & ~(size_t)3));
-      set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
+// Exact projection with W read from LDS (row-major bf16, kDim per row) and
+// the descriptor row loaded up front.
+__device__ __forceinline__ double exact_projection_lds(const uint8_t* xr, const uint16_t* sWr, double c) {
+  u32x4 xv[8];
+#pragma unroll
+  for (int k16 = 0; k16 < kDim / 16; ++k16) xv[k16] = *(gcu32x4*)(xr + 16 * k16);
+  double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
+#pragma unroll
+  for (int k16 = 0; k16 < kDim / 16; ++k16) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const uint2 wv = *reinterpret_cast<const uint2*>(sWr + 16 * k16 + 4 * q);
+      const uint32_t x4 = xv[k16][q];
+      p0 = fma((double)__uint_as_float(wv.x << 16), (double)(x4 & 0xFF), p0);
+      p1 = fma((double)__uint_as_float(wv.x & 0xFFFF0000u), (double)((x4 >> 8) & 0xFF), p1);
+      p2 = fma((double)__uint_as_float(wv.y << 16), (double)((x4 >> 16) & 0xFF), p2);
+      p3 = fma((double)__uint_as_float(wv.y & 0xFFFF0000u), (double)(x4 >> 24), p3);
     }
   }
-  if (gtid == 0) atomicAdd(pc.fixups, (unsigned long long)count);
+  return ((p0 + p1) + (p2 + p3)) - c;
+}
+
+constexpr int kFixWG = 512;
+
+__global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
+  __shared__ uint16_t sW[kRowsPad * kDim];
+  if (pc.fixlist[0] != 0) return;  // overflow: k_fixup_all rebuilds the batch
+  for (int c = threadIdx.x; c < kRowsPad * kDim / 8; c += kFixWG)
+    reinterpret_cast<uint4*>(sW)[c] = reinterpret_cast<const uint4*>(pc.W)[c];
+  __syncthreads();
+  const uint32_t cap_w = pc.fix_cap / pc.n_waves;
+  const uint32_t* counts = pc.fixlist + 1;
+  const uint32_t* entries = pc.fixlist + 1 + pc.n_waves;
+  const int lane = __lane_id();
+  // a wavefront takes whole regions; its lanes stride inside one
+  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kFixWG / 64) + (threadIdx.x >> 6)));
+  const int nw = gridDim.x * (kFixWG / 64);
+  uint32_t done = 0;
+  for (int r = wid; r < pc.n_waves; r += nw) {
+    const uint32_t count = counts[r];
+    for (uint32_t k = lane; k < count; k += 64) {
+      const uint32_t ent = entries[(size_t)r * cap_w + k];
+      const int im = ent >> 24, row = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
+      const HashImage& I = hb.img[im];
+      const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kDim, pc.cmu[row]);
+      if (row < 128) {
+        set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
+      } else {
+        const int t = (row - 128) / hb.m, j = (row - 128) % hb.m;
+        const size_t byte = (size_t)t * I.n_pad + d;
+        uint32_t* w = reinterpret_cast<uint32_t*>(I.ids + (byte & ~(size_t)3));
+        set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
+      }
+    }
+    done += count;
+  }
+  if (lane == 0 && done) atomicAdd(pc.fixups, (unsigned long long)done);
 }
 
 // After an overflow of the fix-up list: rebuild every code and bucket id of
 // the batch from exact values (adversarial inputs only).
 __global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc) {
-  if (pc.fixlist[1] == 0) return;
+  if (pc.fixlist[0] == 0) return;
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gsize = gridDim.x * blockDim.x;
   const int total = hb.tile_prefix[hb.count] * 32;
@@ -321,18 +371,21 @@ hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, i
                           hipStream_t s) {
   const int tiles = hb.tile_prefix[hb.count];
   if (tiles == 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(pc.fixlist, 0u, 2, s);
+  hipError_t e = launch_fill_u32(pc.fixlist, 0u, 1, s);
   if (e != hipSuccess) return e;
   int grid = (tiles + kProjWaves - 1) / kProjWaves;
   if (grid > 2 * n_cu) grid = 2 * n_cu;
+  if (grid * kProjWaves > kMaxProjWaves) grid = kMaxProjWaves / kProjWaves;
+  ProjConsts p2 = pc;
+  p2.n_waves = grid * kProjWaves;
   if (fp32)
-    hipLaunchKernelGGL(k_project<true>, dim3(grid), dim3(kProjWG), 0, s, hb, pc);
+    hipLaunchKernelGGL(k_project<true>, dim3(grid), dim3(kProjWG), 0, s, hb, p2);
   else
-    hipLaunchKernelGGL(k_project<false>, dim3(grid), dim3(kProjWG), 0, s, hb, pc);
+    hipLaunchKernelGGL(k_project<false>, dim3(grid), dim3(kProjWG), 0, s, hb, p2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fixup, dim3(4 * n_cu), dim3(256), 0, s, hb, pc);
-  hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, pc);
+  hipLaunchKernelGGL(k_fixup, dim3(2 * n_cu), dim3(kFixWG), 0, s, hb, p2);
+  hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, p2);
   return hipGetLastError();
 }
 
