@@ -8,6 +8,9 @@ tables for all 50 images, then matching of all 400 pairs in one batched
 launch (persistent kernel replayed from a HIP graph).  The plain per-pair
 path (one launch per pair, host loop) is timed beside it.
 
+Other workloads (--workload strips | knn-200x40000) run the same step on the
+larger synthetic inputs; the default is the one above.
+
 Prints one JSON line.  --gpus N > 1 is not supported: this build runs on one
 GPU.
 """
@@ -40,6 +43,11 @@ def parse():
                     help="only run a plain 256 MiB device copy (counter scaling under rocprofv3)")
     ap.add_argument("--profile", action="store_true", help="few steps, no CPU leg (for rocprofv3)")
     ap.add_argument("--no-plain", action="store_true", help="skip timing the plain per-pair path")
+    ap.add_argument("--workload", default="knn-50x8000",
+                    choices=["knn-50x8000", "strips", "knn-200x40000"])
+    ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
+    ap.add_argument("--no-reuse", action="store_true",
+                    help="also time the plain path re-hashing both images of every pair")
     ap.add_argument("--tuning", default="auto",
                     help="'auto' (autotuner), 'default', or queries_per_item,wg_threads,lds_codes,grid_per_cu")
     return ap.parse_args()
@@ -60,10 +68,15 @@ def main():
     from paper_2505_22089_amd import chm, synth
 
     dev = torch.device("cuda:0")
-    wl = synth.config2()
+    gen = {"knn-50x8000": synth.config2, "strips": synth.config3, "knn-200x40000": synth.config4}
+    print("[bench] generating %s" % args.workload, file=sys.stderr, flush=True)
+    wl = gen[args.workload]()
+    if args.workload != "knn-50x8000" and args.steps == 50:
+        args.steps, args.warmup, args.plain_steps = 5, 2, 1
     n_img = len(wl.images)
     P = len(wl.pairs)
-    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio, precision=chm.PROJ_BF16)
+    prec = chm.PROJ_FP32 if args.precision == "fp32" else chm.PROJ_BF16
+    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio, precision=prec)
     need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256 for x in wl.images)
     arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device=dev)
     store = chm.Store(cfg, wl.W, wl.mu, arena)
@@ -71,6 +84,12 @@ def main():
     ids = list(range(n_img))
     store.load(ids, descs)
     torch.cuda.synchronize()
+    s0 = store.stats()
+    store.rehash(ids)
+    s1 = store.stats()
+    fixups_per_hash = s1.fixups - s0.fixups  # projections recomputed in fp64 by one hash pass
+    flips_per_hash = s1.fixup_flips - s0.fixup_flips  # of those, signs the MFMA sum had wrong
+    print("[bench] %d images loaded and hashed" % n_img, file=sys.stderr, flush=True)
 
     stream = torch.cuda.Stream()
     offs = chm.out_offsets(store, wl.pairs)
@@ -106,6 +125,25 @@ def main():
         pp.close()
         if plain_best is None or dt < plain_best[0]:
             plain_best = (dt, tun)
+    # plain path without reuse: every pair re-hashes both of its images
+    noreuse = None
+    if args.no_reuse:
+        if plain_best:
+            store.set_tuning(**plain_best[1])
+        plans = []
+        with torch.cuda.stream(stream):
+            for p in range(P):
+                plans.append(chm.Plan(store, wl.pairs[p:p + 1], offs[p:p + 2], out_p, None,
+                                      chm.MATCH_PLAIN, stream))
+            stream.synchronize()
+            t1 = time.perf_counter()
+            for p in range(P):
+                store.rehash([int(wl.pairs[p, 0]), int(wl.pairs[p, 1])], stream)
+                plans[p].execute(stream)
+            stream.synchronize()
+            noreuse = P / (time.perf_counter() - t1)
+        for pl in plans:
+            pl.close()
     # batched path: launch shape chosen by the autotuner (results identical)
     if args.tuning == "auto":
         from paper_2505_22089_amd import autotune
@@ -172,23 +210,31 @@ def main():
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_step, 4),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int32",
         "data": "synthetic",
-        "config": {"workload": wl.name + " (50 images x 8000 SIFT-like u8 descriptors, 400 directed "
-                   "8-NN pairs, 40% planted overlap)", "L": wl.L, "m": wl.m, "n": 128, "K": K,
-                   "ratio": "%d/%d" % wl.ratio, "projection": "bf16 MFMA + fp64 fix-up",
+        "config": {"workload": describe(wl), "L": wl.L, "m": wl.m, "n": 128, "K": K,
+                   "ratio": "%d/%d" % wl.ratio, "projection": "%s MFMA + fp64 fix-up" % args.precision,
                    "mode": "batched", "tuning": best, "plain_tuning": plain_best[1] if plain_best else None},
         "plain_pairs_per_s": round(plain_value, 1) if plain_value else None,
+        "plain_noreuse_pairs_per_s": round(noreuse, 1) if noreuse else None,
         "batched_over_plain": round(value / plain_value, 2) if plain_value else None,
         "batched_equals_plain": same,
         "stage_ms": {"hash_all_images": round(hash_ms, 4), "match_all_pairs": round(match_ms, 4)},
         "candidates_per_s": round(cand / (ms_step * 1e-3), 1),
         "dense_equiv_cmp_per_s": round(dense / (ms_step * 1e-3), 1),
         "hash_stage_hbm": {"achieved_GBs": round(hash_gbs, 1), "frac": round(hash_gbs / HBM_PEAK_GBS, 4),
-                           "bytes_per_step": hash_bytes},
+                           "bytes_per_step": hash_bytes,
+                           "fp64_fixups_per_descriptor": round(fixups_per_hash / n_desc, 4),
+                           "mfma_sign_errors_per_descriptor": flips_per_hash / n_desc},
         "roofline": roof,
     }
+    if args.workload != "knn-50x8000":
+        roof["traffic"] = None
 
     if not args.no_cpu:
-        res["cpu_baseline"] = cpu_baseline(wl, out_b.cpu().numpy())
+        print("[bench] cpu baseline", file=sys.stderr, flush=True)
+        if args.workload == "knn-50x8000":
+            res["cpu_baseline"] = cpu_baseline(wl, out_b.cpu().numpy())
+        else:
+            res["cpu_baseline"] = cpu_baseline_sampled(wl, out_b.cpu().numpy(), offs)
     print(json.dumps(res), flush=True)
     plan_b.close()
     store.close()
@@ -217,6 +263,54 @@ def cpu_baseline(wl, gpu_out, min_seconds=10.0, max_reps=8):
             "sample": "the whole step (hash %d images + match all %d pairs) run %d times: %.1f s hashing, "
                       "%.1f s matching" % (len(wl.images), P, reps, t_hash, t_match),
             "gpu_identical_all_pairs": same}
+
+
+def describe(wl):
+    n = np.array([x.shape[0] for x in wl.images])
+    m = wl.meta or {}
+    return ("%s (%d images x %s SIFT-like u8 descriptors, %d directed pairs, %.0f%% mean overlap)"
+            % (wl.name, len(n), ("%d" % n[0]) if n.min() == n.max() else "%d-%d" % (n.min(), n.max()),
+               len(wl.pairs), 100 * m.get("overlap_mean", m.get("target_overlap", 0.0))))
+
+
+def cpu_baseline_sampled(wl, gpu_out, offs, min_seconds=10.0):
+    """The oracle on a random sample of pairs (their images hashed first),
+    grown until about ten seconds of CPU work have run; hashing is scaled to
+    all descriptors and matching to all pairs.  The sampled outputs are
+    compared with the GPU's."""
+    from oracle import oracle as O
+    rng = np.random.default_rng(7)
+    order = rng.permutation(len(wl.pairs))
+    H = [None] * len(wl.images)
+    t_hash = t_match = 0.0
+    n_hashed = n_pairs = 0
+    same = True
+    for c in range(0, len(order), 8):
+        idx = np.sort(order[c:c + 8])
+        sub = wl.pairs[idx]
+        need = sorted({int(i) for i in sub.ravel()} - {i for i in range(len(H)) if H[i] is not None})
+        t0 = time.perf_counter()
+        for i in need:
+            H[i] = O.hash_image(wl.images[i], wl.W, wl.mu, wl.L, wl.m)
+        t1 = time.perf_counter()
+        out, so, _, _ = O.match_pairs(H, sub, wl.L, wl.m, wl.K, wl.ratio)
+        t2 = time.perf_counter()
+        t_hash += t1 - t0
+        t_match += t2 - t1
+        n_hashed += sum(wl.images[i].shape[0] for i in need)
+        n_pairs += len(idx)
+        for k, p in enumerate(idx):
+            same = same and bool(np.array_equal(out[so[k]:so[k + 1]], gpu_out[offs[p]:offs[p + 1]]))
+        if t_hash + t_match >= min_seconds:
+            break
+    n_desc = sum(x.shape[0] for x in wl.images)
+    t_full = t_hash * n_desc / max(1, n_hashed) + t_match * len(wl.pairs) / max(1, n_pairs)
+    return {"value": round(len(wl.pairs) / t_full, 3), "unit": "pairs/s", "cores": O.max_threads(),
+            "kind": "oracle",
+            "sample": "%d random pairs (%d images hashed, %.1f s; matching %.1f s), hashing scaled to "
+                      "%d descriptors and matching to %d pairs" % (n_pairs, sum(h is not None for h in H),
+                                                                   t_hash, t_match, n_desc, len(wl.pairs)),
+            "gpu_identical_on_sample": same}
 
 
 def copy_calibration():

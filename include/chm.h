@@ -66,10 +66,16 @@ typedef struct chm_config {
   int32_t reserved;       /* must be 0 */
   double fixup_rel;       /* a projection p is recomputed in fp64 when
                              |p| < fixup_rel * ||W_r||_2 * ||x - mu||_2;
-                             must lie in [1e-4, 0.5] (1e-3 recommended) */
+                             must lie in [1e-4, 0.5].  The fp32 sum of the
+                             128 exact products errs by at most
+                             127 * 2^-24 * sum|W_rd (x_d - mu_d)|
+                             <= 7.6e-6 * ||W_r||_2 * ||x - mu||_2 (twice that
+                             if the accumulator truncated), so every value
+                             in the range keeps every bit exact; 1e-4 (the
+                             default) recomputes the fewest */
 } chm_config;
 
-/* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-3). */
+/* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-4). */
 void chm_config_default(chm_config *cfg);
 
 /* Message of the last failing call on this thread ("" if none). */
@@ -147,6 +153,7 @@ typedef struct chm_stats {
   int64_t images_evicted;
   int32_t resident_images;
   int32_t reserved;
+  uint64_t fixup_flips;      /* recomputed projections whose bit the MFMA sign had wrong */
 } chm_stats;
 
 chm_status chm_store_stats(chm_store *store, chm_stats *out);
@@ -159,7 +166,11 @@ chm_status chm_store_stats(chm_store *store, chm_stats *out);
  *               members[t][offsets[t][b] .. offsets[t][b+1])
  *   d_members : L x n uint16 db indices, ascending inside each bucket
  *   d_norms   : n uint32, squared norm of each descriptor
- * Any pointer may be NULL to skip that array. */
+ * Any pointer may be NULL to skip that array.  offsets and members are the
+ * plain tables of Sec. 2.3.1 step (1); the device keeps each bucket padded to
+ * a multiple of 8 entries, so asking for either synchronises the stream and
+ * stages them through host memory (CHM_E_INTERNAL if the device tables are
+ * inconsistent). */
 chm_status chm_debug_image(chm_store *store, int32_t image_id, uint32_t *d_codes, uint8_t *d_ids,
                            int32_t *d_offsets, uint16_t *d_members, uint32_t *d_norms,
                            void *stream);

@@ -42,7 +42,8 @@ class Config(C.Structure):
 class Stats(C.Structure):
     _fields_ = [("h2d_bytes", C.c_uint64), ("d2d_bytes", C.c_uint64), ("resident_bytes", C.c_uint64),
                 ("resident_peak", C.c_uint64), ("fixups", C.c_uint64), ("images_loaded", C.c_int64),
-                ("images_evicted", C.c_int64), ("resident_images", C.c_int32), ("reserved", C.c_int32)]
+                ("images_evicted", C.c_int64), ("resident_images", C.c_int32), ("reserved", C.c_int32),
+                ("fixup_flips", C.c_uint64)]
 
 
 class Tuning(C.Structure):
@@ -139,7 +140,7 @@ def _stream(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-3) -> Config:
+def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-4) -> Config:
     c = Config()
     lib().chm_config_default(C.byref(c))
     c.num_tables, c.bucket_bits, c.top_k = L, m, K

@@ -2,12 +2,22 @@
 // buckets as a stable counting sort of the bucket ids (CSR: offsets +
 // members, members ascending inside each bucket).
 //
+// A member is stored as 16 j, the byte offset of db point j's long code, so
+// a matching lane addresses the code with no arithmetic.  Each bucket's range
+// of the members array is padded to a multiple of 8 entries with copies of
+// the bucket's first (smallest) member, and starts at a multiple of 8: a
+// matching lane then reads whole aligned 32-byte blocks of 8 members and
+// needs no bounds test per entry (a repeated member is a candidate already
+// seen, which the set semantics of the candidate list drop).
+// offsets[t][b] .. offsets[t][b + 1] is the padded range.
+//
 // One work-group per (image, table).  The table's ids are staged in LDS once;
 // each wavefront owns a contiguous segment of descriptors.  Pass 1 counts
-// per (wavefront, bucket); a scan turns the counts into each wavefront's
-// starting position inside each bucket; pass 2 scatters, ranking equal ids
-// inside a 64-lane chunk with ballots (lanes agreeing on every id bit), so
-// the order inside a bucket is the descriptor order.
+// per (wavefront, bucket) and finds each bucket's first member; a scan turns
+// the counts into each wavefront's starting position inside each bucket;
+// pass 2 scatters, ranking equal ids inside a 64-lane chunk with ballots
+// (lanes agreeing on every id bit), so the order inside a bucket is the
+// descriptor order; the pads are written last.
 #include "chm_internal.h"
 
 namespace chm {
@@ -29,10 +39,14 @@ __device__ __forceinline__ uint64_t peers_of(uint32_t b, bool valid, int m) {
 __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   __shared__ uint8_t sId[kBucketMaxN];
   __shared__ uint32_t cnt[kBucketWaves][256];
+  __shared__ uint32_t first[256];   // smallest member of each bucket
+  __shared__ uint32_t real[256];    // members of each bucket
+  __shared__ uint32_t pbase[256];   // padded start of each bucket
+  __shared__ uint32_t s_total;      // padded length of the table
 
   const int im = blockIdx.x / hb.L;
   const int t = blockIdx.x % hb.L;
-  const HashImage& I = hb.img[im];
+  const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
   const int n = I.n;
   const int nb = 1 << hb.m;
   const int tid = threadIdx.x;
@@ -44,6 +58,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   for (int i = tid; i < I.n_pad / 8; i += kBucketWG)
     reinterpret_cast<uint2*>(sId)[i] = reinterpret_cast<const uint2*>(ids)[i];
   for (int i = tid; i < kBucketWaves * 256; i += kBucketWG) (&cnt[0][0])[i] = 0;
+  for (int i = tid; i < 256; i += kBucketWG) first[i] = 0xFFFFFFFFu;
   __syncthreads();
 
   // each wavefront: a contiguous segment of whole 64-lane chunks
@@ -57,11 +72,14 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const bool valid = i < n;
     const uint32_t b = valid ? sId[i] : 0u;
     const uint64_t peers = peers_of(b, valid, hb.m);
-    if (valid && (peers & lt) == 0) cnt[wave][b] += (uint32_t)__popcll(peers);
+    if (valid && (peers & lt) == 0) {
+      cnt[wave][b] += (uint32_t)__popcll(peers);
+      atomicMin(&first[b], (uint32_t)i);
+    }
   }
   __syncthreads();
 
-  // offsets of the table, and each wavefront's start inside each bucket
+  // padded offsets of the table, and each wavefront's start inside each bucket
   if (tid < 64) {
     // scan over buckets: lane handles buckets 4*lane .. 4*lane+3
     uint32_t tot[4], run = 0;
@@ -71,8 +89,9 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
       uint32_t s = 0;
       if (b < nb)
         for (int w = 0; w < kBucketWaves; ++w) s += cnt[w][b];
-      tot[k] = s;
-      run += s;
+      if (b < nb) real[b] = s;
+      tot[k] = (s + 7u) & ~7u;
+      run += tot[k];
     }
     uint32_t incl = run;
 #pragma unroll
@@ -86,6 +105,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
       const int b = 4 * lane + k;
       if (b < nb) {
         I.offsets[t * (nb + 1) + b] = (int32_t)base;
+        pbase[b] = base;
         uint32_t pos = base;
         for (int w = 0; w < kBucketWaves; ++w) {
           const uint32_t c = cnt[w][b];
@@ -95,11 +115,14 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
       }
       base += tot[k];
     }
-    if (lane == 63) I.offsets[t * (nb + 1) + nb] = (int32_t)incl;
+    if (lane == 63) {
+      I.offsets[t * (nb + 1) + nb] = (int32_t)incl;
+      s_total = incl;
+    }
   }
   __syncthreads();
 
-  uint16_t* mem = I.members + (size_t)t * I.n_pad;
+  uint32_t* mem = I.members + (size_t)t * I.m_stride;
   for (int c = c0; c < c1; ++c) {
     const int i = c * 64 + lane;
     const bool valid = i < n;
@@ -107,12 +130,17 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const uint64_t peers = peers_of(b, valid, hb.m);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t start = valid ? cnt[wave][b] : 0u;
-    if (valid) mem[start + rank] = (uint16_t)i;
+    if (valid) mem[start + rank] = 16u * (uint32_t)i;
     __builtin_amdgcn_wave_barrier();
     if (valid && rank == 0) cnt[wave][b] = start + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
   }
-  for (int i = n + tid; i < I.n_pad; i += kBucketWG) mem[i] = 0;
+  // pads (positions no scattered member takes) and the unused tail
+  for (int b = tid; b < nb; b += kBucketWG) {
+    const uint32_t c = real[b], pc = (c + 7u) & ~7u;
+    for (uint32_t k = c; k < pc; ++k) mem[pbase[b] + k] = 16u * first[b];
+  }
+  for (int i = (int)s_total + tid; i < I.m_stride; i += kBucketWG) mem[i] = 0;
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {

@@ -53,7 +53,7 @@ extern "C" void chm_config_default(chm_config* cfg) {
   cfg->ratio_num = 4;
   cfg->ratio_den = 5;
   cfg->proj_precision = CHM_PROJ_BF16;
-  cfg->fixup_rel = 1e-3;
+  cfg->fixup_rel = 1e-4;
 }
 
 static chm_status check_config(const chm_config* c) {
@@ -75,20 +75,6 @@ static chm_status check_config(const chm_config* c) {
 
 static inline uint64_t round_up(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
 
-ImageLayout chm::image_layout(int L, int m, int n) {
-  ImageLayout l;
-  const uint64_t nb = 1ull << m;
-  l.n_pad = (int)round_up((uint64_t)n, 8);
-  uint64_t o = 0;
-  l.desc = o;    o += round_up((uint64_t)n * kDim, 256);
-  l.codes = o;   o += round_up((uint64_t)n * 16, 256);
-  l.ids = o;     o += round_up((uint64_t)L * l.n_pad, 256);
-  l.norms = o;   o += round_up((uint64_t)n * 4, 256);
-  l.offsets = o; o += round_up((uint64_t)L * (nb + 1) * 4, 256);
-  l.members = o; o += round_up((uint64_t)L * l.n_pad * 2, 256);
-  l.total = o;
-  return l;
-}
 
 // ------------------------------------------------------------------ arena
 
@@ -206,6 +192,11 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   S->base = (uint8_t*)d_arena;
   S->size = arena_bytes;
   S->n_cu = ncu;
+  {
+    int nx = 1;
+    if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) nx = 1;
+    S->n_xcd = std::min(nx, kMaxBins);
+  }
   S->device = dev;
   S->arena.free_[kHdrBytes] = arena_bytes - kHdrBytes;
   if (arena_bytes == kHdrBytes) S->arena.free_.clear();
@@ -224,8 +215,8 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   if (e == hipSuccess) e = hipMemcpy(S->dTau, tau.data(), tau.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dCmu, cmu.data(), cmu.size() * 8, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dMu, h_mu, kDim, hipMemcpyHostToDevice);
-  unsigned long long zero = 0;
-  if (e == hipSuccess) e = hipMemcpy(S->dFix, &zero, 8, hipMemcpyHostToDevice);
+  unsigned long long zero[2] = {0, 0};  // fix-ups, flips
+  if (e == hipSuccess) e = hipMemcpy(S->dFix, zero, sizeof zero, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete S;
@@ -243,18 +234,11 @@ extern "C" void chm_store_destroy(chm_store* S) {
 }
 
 HashImage chm::hash_image_of(const chm_store* S, const ImageSlot& sl) {
-  const ImageLayout l = image_layout(S->cfg.num_tables, S->cfg.bucket_bits, sl.n);
-  uint8_t* b = S->base + sl.off;
-  HashImage h;
-  h.desc = b + l.desc;
-  h.codes = (uint4*)(b + l.codes);
-  h.ids = b + l.ids;
-  h.norms = (uint32_t*)(b + l.norms);
-  h.offsets = (int32_t*)(b + l.offsets);
-  h.members = (uint16_t*)(b + l.members);
-  h.n = sl.n;
-  h.n_pad = l.n_pad;
-  return h;
+  HashSlot hs;
+  hs.base = S->base + sl.off;
+  hs.n = sl.n;
+  hs.reserved = 0;
+  return hash_image(hs, S->cfg.num_tables, S->cfg.bucket_bits);
 }
 
 chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& slots, hipStream_t s) {
@@ -276,7 +260,8 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
     int descs = 0;
     for (size_t i = i0; i < slots.size() && cnt < kHashBatch; ++i, ++cnt) {
       if (cnt > 0 && descs + slots[i]->n > kHashBatchDescs) break;
-      hb.img[cnt] = hash_image_of(S, *slots[i]);
+      hb.img[cnt].base = S->base + slots[i]->off;
+      hb.img[cnt].n = slots[i]->n;
       hb.tile_prefix[cnt] = tiles;
       tiles += (slots[i]->n + 31) / 32;
       descs += slots[i]->n;
@@ -384,10 +369,11 @@ extern "C" chm_status chm_store_image_feats(const chm_store* S, int32_t id, int3
 extern "C" chm_status chm_store_stats(chm_store* S, chm_stats* out) {
   clear_error();
   if (!S || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
-  unsigned long long f = 0;
   HIPCHK(hipDeviceSynchronize());
-  HIPCHK(hipMemcpy(&f, S->dFix, 8, hipMemcpyDeviceToHost));
-  S->stats.fixups = f;
+  unsigned long long fl[2] = {0, 0};
+  HIPCHK(hipMemcpy(fl, S->dFix, sizeof fl, hipMemcpyDeviceToHost));
+  S->stats.fixups = fl[0];
+  S->stats.fixup_flips = fl[1];
   *out = S->stats;
   return CHM_OK;
 }
@@ -407,11 +393,41 @@ extern "C" chm_status chm_debug_image(chm_store* S, int32_t id, uint32_t* d_code
   if (d_ids && n)
     HIPCHK(hipMemcpy2DAsync(d_ids, n, h.ids, (size_t)h.n_pad, n, L, hipMemcpyDeviceToDevice, s));
   if (d_norms && n) HIPCHK(hipMemcpyAsync(d_norms, h.norms, n * 4, hipMemcpyDeviceToDevice, s));
-  if (d_offsets)
-    HIPCHK(hipMemcpyAsync(d_offsets, h.offsets, (size_t)L * (S->nb + 1) * 4, hipMemcpyDeviceToDevice, s));
-  if (d_members && n)
-    HIPCHK(hipMemcpy2DAsync(d_members, n * 2, h.members, (size_t)h.n_pad * 2, n * 2, L,
-                            hipMemcpyDeviceToDevice, s));
+  if (d_offsets || d_members) {
+    // The device tables hold padded bucket ranges; hand out the plain tables
+    // (each bucket's members only), recovered as the strictly increasing
+    // prefix of each padded range.
+    const size_t nb1 = (size_t)S->nb + 1;
+    std::vector<int32_t> po((size_t)L * nb1), ro((size_t)L * nb1);
+    std::vector<uint32_t> pm((size_t)L * h.m_stride + 1);
+    std::vector<uint16_t> rm((size_t)L * n + 1);
+    HIPCHK(hipMemcpyAsync(po.data(), h.offsets, po.size() * 4, hipMemcpyDeviceToHost, s));
+    if (h.m_stride)
+      HIPCHK(hipMemcpyAsync(pm.data(), h.members, (size_t)L * h.m_stride * 4, hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    for (int t = 0; t < L; ++t) {
+      const int32_t* o = po.data() + t * nb1;
+      const uint32_t* mm = pm.data() + (size_t)t * h.m_stride;
+      size_t pos = 0;
+      for (size_t b = 0; b + 1 < nb1; ++b) {
+        ro[t * nb1 + b] = (int32_t)pos;
+        if (o[b] < 0 || o[b] > o[b + 1] || o[b + 1] > h.m_stride || (o[b] & 7))
+          return fail(CHM_E_INTERNAL, "table %d bucket %zu: bad padded range", t, b);
+        for (int32_t k = o[b]; k < o[b + 1] && (k == o[b] || mm[k] > mm[k - 1]); ++k) {
+          if (pos >= n) return fail(CHM_E_INTERNAL, "table %d holds more than n members", t);
+          if ((mm[k] & 15u) || (mm[k] >> 4) >= n)
+            return fail(CHM_E_INTERNAL, "table %d: member %u is no code offset", t, mm[k]);
+          rm[(size_t)t * n + pos++] = (uint16_t)(mm[k] >> 4);
+        }
+      }
+      ro[t * nb1 + nb1 - 1] = (int32_t)pos;
+      if (pos != n) return fail(CHM_E_INTERNAL, "table %d holds %zu members, not %zu", t, pos, n);
+    }
+    if (d_offsets) HIPCHK(hipMemcpyAsync(d_offsets, ro.data(), ro.size() * 4, hipMemcpyHostToDevice, s));
+    if (d_members && n)
+      HIPCHK(hipMemcpyAsync(d_members, rm.data(), (size_t)L * n * 2, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
   return CHM_OK;
 }
 
@@ -455,6 +471,7 @@ static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
   d.members = h.members;
   d.n = h.n;
   d.n_pad = h.n_pad;
+  d.m_stride = h.m_stride;
   return d;
 }
 
@@ -506,45 +523,80 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
       pl->pair_lds[p] = lds;
     }
   } else {
+    // Items of a class are dealt into one bin per XCD, whole db images at a
+    // time (longest total first onto the least loaded bin), so the work-groups
+    // of an XCD share the db images' codes, members and descriptors in their
+    // L2; inside a bin, a db image's items are consecutive, longest first.
     const int qpi = pl->tun.queries_per_item;
-    std::vector<std::pair<double, WorkItem>> a, b;
-    for (int p = 0; p < P; ++p) {
-      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
-      for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
-        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
-        const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
-        (lds ? a : b).push_back({cost, w});
+    const int nbins = std::max(1, S->n_xcd);
+    for (int cls = 0; cls < 2; ++cls) {
+      std::map<const void*, std::vector<std::pair<double, WorkItem>>> groups;
+      for (int p = 0; p < P; ++p) {
+        const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+        if (lds != (cls == 0)) continue;
+        for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
+          WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
+          const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
+          groups[pd[p].d.codes].push_back({cost, w});
+        }
       }
+      std::vector<std::pair<double, std::vector<std::pair<double, WorkItem>>*>> order;
+      for (auto& g : groups) {
+        double c = 0;
+        for (auto& x : g.second) c += x.first;
+        std::sort(g.second.begin(), g.second.end(),
+                  [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
+                    if (x.first != y.first) return x.first > y.first;
+                    if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
+                    return x.second.q0 < y.second.q0;
+                  });
+        order.push_back({c, &g.second});
+      }
+      std::stable_sort(order.begin(), order.end(),
+                       [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<std::vector<WorkItem>> bins(nbins);
+      std::vector<double> load(nbins, 0.0);
+      for (auto& g : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += g.first;
+        for (auto& x : *g.second) bins[b].push_back(x.second);
+      }
+      int32_t* bb = pl->bins[cls];
+      bb[0] = (int32_t)items.size();
+      for (int b = 0; b < nbins; ++b) {
+        items.insert(items.end(), bins[b].begin(), bins[b].end());
+        bb[b + 1] = (int32_t)items.size();
+      }
+      pl->n_bins = nbins;
+      if (cls == 0) pl->n_lds_items = (int)items.size();
     }
-    auto byc = [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
-      if (x.first != y.first) return x.first > y.first;
-      if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
-      return x.second.q0 < y.second.q0;
-    };
-    std::sort(a.begin(), a.end(), byc);
-    std::sort(b.begin(), b.end(), byc);
-    for (auto& x : a) items.push_back(x.second);
-    for (auto& x : b) items.push_back(x.second);
-    pl->n_lds_items = (int)a.size();
   }
   pl->n_items = (int)items.size();
 
   const uint64_t pairs_bytes = round_up(sizeof(PairDev) * (size_t)std::max(P, 1), 256);
   const uint64_t items_bytes = round_up(sizeof(WorkItem) * (size_t)std::max(pl->n_items, 1), 256);
-  pl->mem_bytes = pairs_bytes + items_bytes + 256;
+  const uint64_t queue_bytes = 256;  // 2 x kMaxBins counters
+  const uint64_t bins_bytes = 256;   // 2 x (kMaxBins + 1) offsets, relative to the class
+  static_assert(2 * kMaxBins * 4 <= 256 && 2 * (kMaxBins + 1) * 4 <= 256, "plan tail");
+  pl->mem_bytes = pairs_bytes + items_bytes + queue_bytes + bins_bytes;
   if (!S->arena.alloc(pl->mem_bytes, &pl->mem_off)) {
     delete pl;
     return fail(CHM_E_CAPACITY, "arena cannot hold the plan's work list (%llu bytes)",
-                (unsigned long long)(pairs_bytes + items_bytes + 256));
+                (unsigned long long)pl->mem_bytes);
   }
   pl->dPairs = (PairDev*)(S->base + pl->mem_off);
   pl->dItems = (WorkItem*)(S->base + pl->mem_off + pairs_bytes);
   pl->dQueue = (uint32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes);
+  pl->dBins = (int32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes + queue_bytes);
+  int32_t hbins[2][kMaxBins + 1] = {};
+  for (int cls = 0; cls < 2; ++cls)
+    for (int b = 0; b <= pl->n_bins; ++b) hbins[cls][b] = pl->bins[cls][b] - pl->bins[cls][0];
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (P) e = hipMemcpyAsync(pl->dPairs, pd.data(), sizeof(PairDev) * P, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && pl->n_items)
     e = hipMemcpyAsync(pl->dItems, items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, hbins, sizeof hbins, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     S->arena.release(pl->mem_off, pl->mem_bytes);
@@ -558,6 +610,8 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   a.n_items = 0;
   a.item_base = 0;
   a.queue = pl->dQueue;
+  a.bin_begin = pl->dBins;
+  a.n_bins = 1;
   a.out = d_out;
   a.topk = d_topk;
   a.L = S->cfg.num_tables;
@@ -570,21 +624,25 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {
     hipStream_t cs = S->cap_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, 2, cs);
+    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, 2 * kMaxBins, cs);
     const int nl = pl->n_lds_items, ng = pl->n_items - pl->n_lds_items;
     if (e == hipSuccess && nl > 0) {
       MatchArgs x = a;
       x.items = pl->dItems;
       x.n_items = nl;
       x.queue = pl->dQueue;
-      const int grid = std::min(nl, S->n_cu * (pl->tun.wg_threads == 1024 ? 1 : 1));
+      x.bin_begin = pl->dBins;
+      x.n_bins = pl->n_bins;
+      const int grid = std::min(nl, S->n_cu);  // the LDS stage allows one work-group per CU
       e = launch_match(x, a.K, pl->tun.wg_threads, true, true, grid, cs);
     }
     if (e == hipSuccess && ng > 0) {
       MatchArgs x = a;
       x.items = pl->dItems + nl;
       x.n_items = ng;
-      x.queue = pl->dQueue + 1;
+      x.queue = pl->dQueue + kMaxBins;
+      x.bin_begin = pl->dBins + (kMaxBins + 1);
+      x.n_bins = pl->n_bins;
       x.lds_max_feats = 0;
       const int grid = std::min(ng, S->n_cu * pl->tun.grid_per_cu);
       e = launch_match(x, a.K, 256, false, true, grid, cs);

@@ -23,11 +23,7 @@ struct Arena {
   void release(uint64_t off, uint64_t bytes);
 };
 
-struct ImageLayout {
-  uint64_t desc, codes, ids, norms, offsets, members, total;
-  int n_pad;
-};
-ImageLayout image_layout(int L, int m, int n);
+
 
 struct ImageSlot {
   uint64_t off = 0;
@@ -56,6 +52,7 @@ struct chm_store {
   chm_stats stats;
   chm_tuning tuning;
   int n_cu = 0;
+  int n_xcd = 1;  // XCDs of the device (work-groups are dealt to them round-robin)
   int device = 0;
   hipStream_t cap_stream = nullptr;
 };
@@ -66,6 +63,8 @@ struct chm_plan {
   int n_pairs = 0;
   int n_items = 0;
   int n_lds_items = 0;
+  int n_bins = 1;
+  int32_t bins[2][chm::kMaxBins + 1] = {};  // item offsets of the bins (absolute)
   int lds_max = 0;
   int32_t* out = nullptr;
   uint32_t* topk = nullptr;
@@ -73,7 +72,8 @@ struct chm_plan {
   uint64_t mem_off = 0, mem_bytes = 0;
   chm::PairDev* dPairs = nullptr;
   chm::WorkItem* dItems = nullptr;
-  uint32_t* dQueue = nullptr;
+  uint32_t* dQueue = nullptr;  // 2 x kMaxBins counters (LDS class, global class)
+  int32_t* dBins = nullptr;    // 2 x (kMaxBins + 1) bin offsets
   std::vector<int> pair_begin, pair_count;
   std::vector<char> pair_lds;
   chm::MatchArgs args;

@@ -18,10 +18,12 @@ struct ImageDev {
   const uint4* codes;       // n: long code, bit r in word r/32 at r%32
   const uint8_t* ids;       // L x n_pad: bucket id of each descriptor, table-major
   const uint32_t* norms;    // n: squared L2 norm
-  const int32_t* offsets;   // L x (nb + 1)
-  const uint16_t* members;  // L x n_pad, ascending inside each bucket
+  const int32_t* offsets;   // L x (nb + 1): padded bucket ranges, multiples of 8
+  const uint32_t* members;  // L x m_stride code byte offsets (16 j), ascending inside each
+                            // bucket, then pads
   int32_t n;
   int32_t n_pad;
+  int32_t m_stride;         // members per table: n + 7 * min(nb, n), rounded up to 8
 };
 
 struct PairDev {
@@ -37,12 +39,18 @@ struct WorkItem {
   int32_t lds;  // 1 if the db image's codes fit the LDS stage of the kernel
 };
 
+// Persistent launches split their items into bins, one per XCD (each XCD
+// has its own L2): bin b holds items[bin_begin[b] .. bin_begin[b+1]).
+constexpr int kMaxBins = 16;
+
 struct MatchArgs {
   const PairDev* pairs;
   const WorkItem* items;
   int32_t n_items;
   int32_t item_base;      // non-persistent launches: first item of the launch
-  uint32_t* queue;        // persistent launches: dequeue counter (zeroed per run)
+  uint32_t* queue;        // persistent launches: one dequeue counter per bin (zeroed per run)
+  const int32_t* bin_begin;  // persistent launches: n_bins + 1 item offsets
+  int32_t n_bins;
   int32_t* out;
   uint32_t* topk;         // optional, K keys per output element
   int32_t L;
@@ -53,8 +61,47 @@ struct MatchArgs {
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
 };
 
-// Hashing of a batch of images, passed by value.
+// Sections of one image slot in the arena (byte offsets from the slot
+// start, each 256-byte aligned): descriptors n x 128, long codes n x 16,
+// bucket ids L x n_pad, squared norms n x 4, offsets L x (2^m + 1) int32,
+// members L x m_stride u32.  Used by the host to size and address slots and
+// by the hashing kernels to address a slot from its base alone.
+struct ImageLayout {
+  uint64_t desc, codes, ids, norms, offsets, members, total;
+  int n_pad;
+  int m_stride;
+};
+
+__host__ __device__ inline uint64_t layout_round(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
+
+__host__ __device__ inline ImageLayout image_layout(int L, int m, int n) {
+  ImageLayout l;
+  const uint64_t nb = 1ull << m;
+  l.n_pad = (int)layout_round((uint64_t)n, 8);
+  // each bucket padded to a multiple of 8 members: at most 7 pads per
+  // non-empty bucket
+  l.m_stride = (int)layout_round((uint64_t)n + 7 * ((uint64_t)n < nb ? (uint64_t)n : nb), 8);
+  uint64_t o = 0;
+  l.desc = o;    o += layout_round((uint64_t)n * kDim, 256);
+  l.codes = o;   o += layout_round((uint64_t)n * 16, 256);
+  l.ids = o;     o += layout_round((uint64_t)L * l.n_pad, 256);
+  l.norms = o;   o += layout_round((uint64_t)n * 4, 256);
+  l.offsets = o; o += layout_round((uint64_t)L * (nb + 1) * 4, 256);
+  l.members = o; o += layout_round((uint64_t)L * l.m_stride * 4, 256);
+  l.total = o;
+  return l;
+}
+
+// Hashing of a batch of images.  The batch is a kernel argument, so it only
+// carries each image's slot base and size (the kernel argument block stays
+// far below 4 KiB); kernels expand an entry with hash_image().
 constexpr int kHashBatch = 64;
+
+struct HashSlot {
+  uint8_t* base;
+  int32_t n;
+  int32_t reserved;
+};
 
 struct HashImage {
   const uint8_t* desc;
@@ -62,31 +109,49 @@ struct HashImage {
   uint8_t* ids;             // L x n_pad, table-major
   uint32_t* norms;
   int32_t* offsets;
-  uint16_t* members;
+  uint32_t* members;        // 16 * db index (the byte offset of its code)
   int32_t n;
   int32_t n_pad;
+  int32_t m_stride;
 };
 
 struct HashBatch {
-  HashImage img[kHashBatch];
+  HashSlot img[kHashBatch];
   int32_t tile_prefix[kHashBatch + 1];  // 32-descriptor tiles before image i
   int32_t count;
   int32_t L;
   int32_t m;
 };
 
+__host__ __device__ inline HashImage hash_image(const HashSlot& s, int L, int m) {
+  const ImageLayout l = image_layout(L, m, s.n);
+  HashImage h;
+  h.desc = s.base + l.desc;
+  h.codes = reinterpret_cast<uint4*>(s.base + l.codes);
+  h.ids = s.base + l.ids;
+  h.norms = reinterpret_cast<uint32_t*>(s.base + l.norms);
+  h.offsets = reinterpret_cast<int32_t*>(s.base + l.offsets);
+  h.members = reinterpret_cast<uint32_t*>(s.base + l.members);
+  h.n = s.n;
+  h.n_pad = l.n_pad;
+  h.m_stride = l.m_stride;
+  return h;
+}
+
 struct ProjConsts {
   const uint16_t* W;        // kRowsPad x 128 bf16 bits (rows >= R are zero)
   const float* tau;         // kRowsPad: fixup_rel * ||W_r|| (rounded up), 0 for padding
   const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
-  unsigned long long* fixups;  // running count of fp64 recomputes
+  unsigned long long* fixups;  // running counts: [0] fp64 recomputes, [1] bits they changed
   uint32_t* fixlist;        // [0] overflow flag, [1..n_waves] per-wave counts, then
                             // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d)
   uint32_t fix_cap;         // entries the list holds
   int32_t n_waves;          // projection wavefronts of the launch (set by launch_project)
   int32_t R;                // 128 + L*m
 };
+
+static_assert(sizeof(HashBatch) + sizeof(ProjConsts) <= 2048, "hashing kernel arguments too large");
 
 // Fix-up list capacity and the per-batch descriptor budget that keeps the
 // expected list (about 1.6 entries per descriptor) well inside it.

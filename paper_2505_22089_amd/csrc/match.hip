@@ -9,19 +9,22 @@
 //      paper's ranking by Hamming distance with ties broken by db index;
 //  (3) it keeps the KT smallest distinct keys in registers: a sorted list
 //      updated with median-of-three steps; a key equal to a kept one is a
-//      candidate an earlier table already returned and is dropped, which
-//      makes the candidate list a set (a key equal to the last kept one
-//      leaves the list unchanged, so it needs no test).  Keys of a block of
-//      eight candidates are computed first; only those below the current
-//      KT-th key are inserted, each lane looping over its own passes;
+//      candidate an earlier table already returned (or a pad of the bucket,
+//      a copy of its first member) and is dropped, which makes the
+//      candidate list a set (a key equal to the last kept one leaves the
+//      list unchanged, so it needs no test).  Keys of a block of eight
+//      candidates are computed first; only those below the current KT-th
+//      key are inserted, one per lane per round, selected with wave masks;
 //  (4) for the first K kept candidates it computes the exact squared distance
 //      ||x||^2 + ||y||^2 - 2 x.y with packed-u8 dot products and int32
 //      accumulation, and applies the ratio test on squared distances
 //      (den^2 * d1 < num^2 * d2).
 //
 // Work items are (pair, query range).  Batched plans run one persistent grid
-// that dequeues items with an atomic counter; inside a work-group, wavefronts
-// take 64-query chunks of the item dynamically.  Plain plans launch one grid
+// that dequeues items with atomic counters, one bin of items per XCD (the
+// items of a db image share a bin, so its data stays in that XCD's L2);
+// inside a work-group, wavefronts take 64-query chunks of the item
+// dynamically.  Plain plans launch one grid
 // per pair.  With LDSC the db image's codes and bucket offsets are staged in
 // LDS once per item (skipped when consecutive items share the db image).
 #include "chm_internal.h"
@@ -71,15 +74,40 @@ __device__ __forceinline__ void insert_unique(uint32_t (&top)[KT], uint32_t key)
   top[0] = min(top[0], key);
 }
 
+typedef __attribute__((address_space(3))) const v4u lds_v4u;
+
+// Long code of the db point whose code lies at byte offset off (16 j): in
+// LDS the staged codes start at LDS address 0 (the kernel has no static LDS,
+// which launch_one checks), so off is the LDS address itself.
 template <bool LDSC>
-__device__ __forceinline__ uint4 code_of(const uint4* sCodes, const uint4* gCodes, uint32_t j) {
-  if (LDSC) return sCodes[j];
-  return ldg4(gCodes + j);
+__device__ __forceinline__ uint4 code_at(const char* gCodes, uint32_t off) {
+  if (LDSC) {
+    const v4u v = *reinterpret_cast<lds_v4u*>((size_t)off);
+    return make_uint4(v.x, v.y, v.z, v.w);
+  }
+  return ldg4(gCodes + off);
+}
+
+// A pointer that is the same in every lane, kept in SGPRs.  readfirstlane
+// returns int: each half goes through uint32_t before widening, so the low
+// half is not sign-extended into the high one.
+__device__ __forceinline__ const char* uniform_ptr(const void* p) {
+  const uint64_t v = reinterpret_cast<uint64_t>(p);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)(v >> 32));
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)v);
+  return reinterpret_cast<const char*>(((uint64_t)hi << 32) | (uint64_t)lo);
+}
+
+// Per lane: cond (bit of this lane in the wave mask `lanes`) ? t : f.
+__device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t t, uint32_t f) {
+  uint32_t r;
+  asm("v_cndmask_b32 %0, %1, %2, %3" : "=v"(r) : "v"(f), "v"(t), "s"(lanes));
+  return r;
 }
 
 template <int KT, bool LDSC>
 __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P, int q,
-                                            const uint4* sCodes, const int32_t* offs) {
+                                            const int32_t* offs) {
   const uint4 qc = ldg4(P.q.codes + q);
   uint32_t qb0 = 0, qb1 = 0;  // bucket ids of the query, one byte per table
   for (int t = 0; t < a.L; ++t) {
@@ -92,69 +120,97 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   for (int k = 0; k < KT; ++k) top[k] = kNoKey;
   uint32_t thr = kNoKey;  // top[KT - 1] as of the last block
 
-  const uint16_t* members = P.d.members;
-  const int n_pad = P.d.n_pad;
+  // Members of table t start at byte 4 * t * m_stride; bucket ranges are
+  // padded to whole aligned blocks of 8, so every slot of a block is a
+  // member of the bucket or a copy of its first member.  A member is the
+  // byte offset 16 j of db point j's code, and keys (h << 24) | 16 j order
+  // like (h, j).
+  const char* mbase = uniform_ptr(P.d.members);
+  const char* gcodes = uniform_ptr(P.d.codes);
+  const uint32_t mstride = 4u * (uint32_t)P.d.m_stride;
   const int stride = a.nb + 1;
-  // Walk the L buckets as one sequence of aligned 8-member blocks.
-  int t = -1, s = 0, e = 0, p = 0;
+  // Walk the L buckets as one sequence of aligned 8-member blocks; toff and
+  // ob follow table t (byte offset of its members, index of its offsets).
+  int t = -1, p = 0, e = 0, ob = -stride;
+  uint32_t toff = 0u - mstride;
   auto next_table = [&]() {
     for (++t; t < a.L; ++t) {
+      toff += mstride;
+      ob += stride;
       const uint32_t b = ((t < 4 ? qb0 >> (8 * t) : qb1 >> (8 * (t - 4)))) & 0xFFu;
-      s = offs[t * stride + b];
-      e = offs[t * stride + b + 1];
-      if (s < e) {
-        p = s & ~7;
-        return;
-      }
+      p = offs[ob + b];
+      e = offs[ob + b + 1];
+      if (p < e) return;
     }
   };
-  next_table();
-  uint4 blk = make_uint4(0, 0, 0, 0);
-  if (t < a.L) blk = ldg4(members + (size_t)t * n_pad + p);
-  while (t < a.L) {
-    const uint4 cur = blk;
-    const int base = p - s;       // slot k holds position p + k; valid iff 0 <= base + k < len
-    const int len = e - s;
-    p += 8;
-    if (p >= e) next_table();
-    if (t < a.L) blk = ldg4(members + (size_t)t * n_pad + p);
-    const uint32_t w[4] = {cur.x, cur.y, cur.z, cur.w};
-    // Keys of the block; a slot passes when it could enter the kept list
-    // (key below the current KT-th key).  Only passing slots are inserted,
-    // lane by lane, so the insertion cost follows each lane's own passes.
+  // One block of 8 slots: keys, then insertion of those that pass.
+  auto process = [&](const uint4& x0, const uint4& x1) {
+    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    // Keys of the block, and per slot the wave mask of lanes whose key
+    // could enter the kept list (below the current KT-th key).
     uint32_t key[8];
-    uint32_t pmask = 0;  // slot k at bit 7 - k
+    uint64_t pass[8];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-      const uint32_t j = (k & 1) ? (w[k >> 1] >> 16) : (w[k >> 1] & 0xFFFFu);
-      const uint4 c = code_of<LDSC>(sCodes, P.d.codes, j);
+      const uint4 c = code_at<LDSC>(gcodes, w[k]);
       const uint32_t h =
           bcnt_acc(qc.w ^ c.w, bcnt_acc(qc.z ^ c.z, bcnt_acc(qc.y ^ c.y, bcnt_acc(qc.x ^ c.x, 0u))));
-      key[k] = (h << 24) | j;
-      pmask = shift_in(pmask, __ballot(key[k] < thr));
+      key[k] = (h << 24) | w[k];
+      pass[k] = __ballot(key[k] < thr);
     }
-    // slots outside [s, e): k < -base or k >= len - base
-    {
-      const int lo = max(0, -base), hi = min(8, len - base);
-      const uint32_t valid = (0xFFu >> lo) & ~(0xFFu >> hi);
-      pmask &= valid;
-    }
-    while (pmask) {
-      const uint32_t i = 7u - (31u - __builtin_clz(pmask));
-      pmask &= ~(0x80u >> i);
-      const uint32_t s01 = (i & 1) ? key[1] : key[0], s23 = (i & 1) ? key[3] : key[2];
-      const uint32_t s45 = (i & 1) ? key[5] : key[4], s67 = (i & 1) ? key[7] : key[6];
-      const uint32_t s03 = (i & 2) ? s23 : s01, s47 = (i & 2) ? s67 : s45;
-      insert_unique<KT>(top, (i & 4) ? s47 : s03);
+    // Insert the passing keys: each round every lane takes its lowest
+    // remaining passing slot (lanes with none take kNoKey, a no-op), so the
+    // rounds follow the largest per-lane pass count of the wave and the
+    // selection runs on the wave masks.
+    uint64_t any = pass[0] | pass[1] | pass[2] | pass[3] | pass[4] | pass[5] | pass[6] | pass[7];
+    while (any) {
+      uint32_t x = kNoKey;
+#pragma unroll
+      for (int k = 7; k >= 0; --k) x = sel_lanes(pass[k], key[k], x);
+      uint64_t seen = 0;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const uint64_t rest = pass[k] & seen;
+        seen |= pass[k];
+        pass[k] = rest;
+      }
+      any = pass[0] | pass[1] | pass[2] | pass[3] | pass[4] | pass[5] | pass[6] | pass[7];
+      insert_unique<KT>(top, x);
     }
     thr = top[KT - 1];
+  };
+  auto load = [&](uint4& x0, uint4& x1) {
+    x0 = ldg4(mbase + (toff + 4u * (uint32_t)p));
+    x1 = ldg4(mbase + (toff + 4u * (uint32_t)p + 16u));
+  };
+  auto advance = [&]() {
+    p += 8;
+    if (p >= e) next_table();
+    return t < a.L;
+  };
+  // Two register sets in turn: the next block loads while this one is used.
+  next_table();
+  if (t < a.L) {
+    uint4 A0, A1, B0, B1;
+    load(A0, A1);
+    for (;;) {
+      const bool more_b = advance();
+      if (more_b) load(B0, B1);
+      process(A0, A1);
+      if (!more_b) break;
+      const bool more_a = advance();
+      if (more_a) load(A0, A1);
+      process(B0, B1);
+      if (!more_a) break;
+    }
   }
 
   const int64_t o = P.out_off + q;
-  if (a.topk) {
+  if (a.topk) {  // keys as (h << 24) | j
 #pragma unroll
     for (int k = 0; k < KT; ++k)
-      if (k < a.K) a.topk[o * a.K + k] = top[k];
+      if (k < a.K)
+        a.topk[o * a.K + k] = top[k] == kNoKey ? kNoKey : (top[k] & 0xFF000000u) | ((top[k] & 0xFFFFFFu) >> 4);
   }
 
   // Euclidean re-rank of the first K candidates and ratio test.
@@ -168,7 +224,7 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
 #pragma unroll
   for (int k = 0; k < KT; ++k) {
     if (k < a.K && top[k] != kNoKey) {
-      const uint32_t j = top[k] & 0xFFFFFFu;
+      const uint32_t j = (top[k] & 0xFFFFFFu) >> 4;
       const uint4* yp = reinterpret_cast<const uint4*>(P.d.desc + (size_t)j * kDim);
       uint32_t dot = 0;
 #pragma unroll
@@ -197,7 +253,7 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
 
 template <int KT, bool LDSC, int WG>
 __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, const WorkItem& w,
-                                         const uint4* sCodes, const int32_t* offs, int* s_chunk) {
+                                         const int32_t* offs, int* s_chunk) {
   // Wavefronts take 64-query chunks of the item in turn.
   const int lane = __lane_id();
   for (;;) {
@@ -206,27 +262,51 @@ __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, c
     c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));  // uniform across the wave
     const int q = w.q0 + c + lane;
     if (w.q0 + c >= w.q1) break;
-    if (q < w.q1) match_query<KT, LDSC>(a, P, q, sCodes, offs);
+    if (q < w.q1) match_query<KT, LDSC>(a, P, q, offs);
   }
 }
 
 template <int KT, int WG, bool LDSC, bool PERSIST>
 __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
+  // All LDS is dynamic and the codes come first, at LDS address 0, so a
+  // code's LDS address is its member value (16 j) itself.
   extern __shared__ uint4 smem[];
-  __shared__ int s_item;
-  __shared__ int s_chunk;
-  const int ncodes = a.lds_max_feats;
+  const int ncodes = LDSC ? a.lds_max_feats : 0;
+  const int noffs = LDSC ? a.L * (a.nb + 1) : 0;
   uint4* sCodes = smem;
-  int32_t* sOffs = reinterpret_cast<int32_t*>(smem + (LDSC ? ncodes : 0));
+  int32_t* sOffs = reinterpret_cast<int32_t*>(smem + ncodes);
+  int* sCtl = reinterpret_cast<int*>(smem + ncodes + (noffs + 3) / 4);
+  int& s_item = sCtl[0];
+  int& s_chunk = sCtl[1];
   const uint4* staged = nullptr;
   int it = PERSIST ? 0 : a.item_base + (int)blockIdx.x;
+  // Persistent: start with the bin of this work-group's XCD (work-groups
+  // are dealt to the XCDs round-robin), then help the other bins in turn.
+  // Each bin is left after one failed dequeue, so every work-group ends
+  // after at most n_items + n_bins dequeues.
+  int bin = PERSIST ? (int)(blockIdx.x % (unsigned)a.n_bins) : 0, visited = 0;
 
   for (;;) {
     if (PERSIST) {
-      if (threadIdx.x == 0) s_item = (int)atomicAdd(a.queue, 1u);
+      if (threadIdx.x == 0) {
+        int got = -1;
+        while (visited < a.n_bins) {
+          const int b0 = a.bin_begin[bin], b1 = a.bin_begin[bin + 1];
+          if (b0 < b1) {
+            const int i = (int)atomicAdd(a.queue + bin, 1u);
+            if (i < b1 - b0) {
+              got = b0 + i;
+              break;
+            }
+          }
+          bin = bin + 1 == a.n_bins ? 0 : bin + 1;
+          ++visited;
+        }
+        s_item = got;
+      }
       __syncthreads();
       it = __builtin_amdgcn_readfirstlane(s_item);  // uniform: item fields in SGPRs
-      if (it >= a.n_items) break;
+      if (it < 0) break;
     }
     if (threadIdx.x == 0) s_chunk = 0;
     const WorkItem w = a.items[it];
@@ -239,22 +319,31 @@ __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
     }
     __syncthreads();
     if (use_lds)
-      run_item<KT, true, WG>(a, P, w, sCodes, sOffs, &s_chunk);
+      run_item<KT, true, WG>(a, P, w, sOffs, &s_chunk);
     else
-      run_item<KT, false, WG>(a, P, w, nullptr, P.d.offsets, &s_chunk);
+      run_item<KT, false, WG>(a, P, w, P.d.offsets, &s_chunk);
     __syncthreads();
     if (!PERSIST) break;
   }
 }
 
 size_t match_lds_bytes(int lds_max_feats, int L, int nb) {
-  return (size_t)lds_max_feats * sizeof(uint4) + (size_t)L * (nb + 1) * sizeof(int32_t);
+  const size_t offs = ((size_t)L * (nb + 1) + 3) / 4 * sizeof(uint4);
+  return (size_t)lds_max_feats * sizeof(uint4) + offs + sizeof(uint4);  // + the two control words
 }
 
 template <int KT, int WG, bool LDSC, bool PERSIST>
 static hipError_t launch_one(const MatchArgs& a, int grid, hipStream_t s) {
-  const size_t lds = LDSC ? match_lds_bytes(a.lds_max_feats, a.L, a.nb) : 0;
+  const size_t lds = LDSC ? match_lds_bytes(a.lds_max_feats, a.L, a.nb) : sizeof(uint4);
   auto fn = k_match<KT, WG, LDSC, PERSIST>;
+  static int static_lds = -1;  // the code stage must start at LDS address 0
+  if (static_lds < 0) {
+    hipFuncAttributes attr;
+    hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(fn));
+    if (e != hipSuccess) return e;
+    static_lds = (int)attr.sharedSizeBytes;
+  }
+  if (static_lds != 0) return hipErrorInvalidKernelFile;
   if (LDSC) {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

@@ -91,7 +91,7 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
   for (int tile = blockIdx.x * kProjWaves + wave; tile < total_tiles;
        tile += gridDim.x * kProjWaves) {
     while (tile >= hb.tile_prefix[im + 1]) ++im;
-    const HashImage& I = hb.img[im];
+    const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
     const int d0 = (tile - hb.tile_prefix[im]) * 32;
     const int dr = d0 + col;
     const bool valid = dr < I.n;
@@ -272,9 +272,10 @@ __device__ __forceinline__ double exact_projection(const uint8_t* xr, const uint
   return ((p0 + p1) + (p2 + p3)) - c;
 }
 
-__device__ __forceinline__ void set_bit(uint32_t* word, uint32_t bit, bool on) {
-  if (on) atomicOr(word, bit);
-  else atomicAnd(word, ~bit);
+// Sets or clears one bit; true when that changed it.
+__device__ __forceinline__ bool set_bit(uint32_t* word, uint32_t bit, bool on) {
+  const uint32_t old = on ? atomicOr(word, bit) : atomicAnd(word, ~bit);
+  return ((old & bit) != 0) != on;
 }
 
 // Exact projection with W read from LDS (row-major bf16, kDim per row) and
@@ -314,26 +315,29 @@ __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
   // a wavefront takes whole regions; its lanes stride inside one
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kFixWG / 64) + (threadIdx.x >> 6)));
   const int nw = gridDim.x * (kFixWG / 64);
-  uint32_t done = 0;
+  uint32_t done = 0, flips = 0;
   for (int r = wid; r < pc.n_waves; r += nw) {
     const uint32_t count = counts[r];
     for (uint32_t k = lane; k < count; k += 64) {
       const uint32_t ent = entries[(size_t)r * cap_w + k];
       const int im = ent >> 24, row = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
-      const HashImage& I = hb.img[im];
+      const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
       const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kDim, pc.cmu[row]);
+      bool changed;
       if (row < 128) {
-        set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
+        changed = set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
       } else {
         const int t = (row - 128) / hb.m, j = (row - 128) % hb.m;
         const size_t byte = (size_t)t * I.n_pad + d;
         uint32_t* w = reinterpret_cast<uint32_t*>(I.ids + (byte & ~(size_t)3));
-        set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
+        changed = set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
       }
+      flips += __popcll(__ballot(changed));
     }
     done += count;
   }
   if (lane == 0 && done) atomicAdd(pc.fixups, (unsigned long long)done);
+  if (lane == 0 && flips) atomicAdd(pc.fixups + 1, (unsigned long long)flips);
 }
 
 // After an overflow of the fix-up list: rebuild every code and bucket id of
@@ -346,7 +350,7 @@ __global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc) 
   for (int g = gtid; g < total; g += gsize) {
     int im = 0;
     while (g >= hb.tile_prefix[im + 1] * 32) ++im;
-    const HashImage& I = hb.img[im];
+    const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
     const int d = g - hb.tile_prefix[im] * 32;
     if (d >= I.n) continue;
     uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
@@ -358,11 +362,17 @@ __global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc) 
       w0 |= slot == 0 ? bit : 0u; w1 |= slot == 1 ? bit : 0u; w2 |= slot == 2 ? bit : 0u;
       w3 |= slot == 3 ? bit : 0u; w4 |= slot == 4 ? bit : 0u; w5 |= slot == 5 ? bit : 0u;
     }
+    const uint4 old = I.codes[d];
+    uint32_t flips = __popc(old.x ^ w0) + __popc(old.y ^ w1) + __popc(old.z ^ w2) + __popc(old.w ^ w3);
     I.codes[d] = make_uint4(w0, w1, w2, w3);
     const uint64_t bb = (uint64_t)w4 | ((uint64_t)w5 << 32);
     const uint32_t mask = (1u << hb.m) - 1u;
-    for (int t = 0; t < hb.L; ++t)
-      I.ids[(size_t)t * I.n_pad + d] = (uint8_t)((uint32_t)(bb >> (hb.m * t)) & mask);
+    for (int t = 0; t < hb.L; ++t) {
+      const uint8_t nb = (uint8_t)((uint32_t)(bb >> (hb.m * t)) & mask);
+      flips += __popc((uint32_t)(I.ids[(size_t)t * I.n_pad + d] ^ nb));
+      I.ids[(size_t)t * I.n_pad + d] = nb;
+    }
+    if (flips) atomicAdd(pc.fixups + 1, (unsigned long long)flips);
   }
   if (gtid == 0) atomicAdd(pc.fixups, (unsigned long long)total * pc.R);
 }

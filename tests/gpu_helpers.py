@@ -10,7 +10,7 @@ def device():
     return torch.device("cuda:0")
 
 
-def new_store(wl, precision=chm.PROJ_BF16, K=None, L=None, m=None, extra=64 << 20, fixup_rel=1e-3):
+def new_store(wl, precision=chm.PROJ_BF16, K=None, L=None, m=None, extra=64 << 20, fixup_rel=1e-4):
     cfg = chm.config(L=wl.L if L is None else L, m=wl.m if m is None else m,
                      K=wl.K if K is None else K, ratio=wl.ratio, precision=precision,
                      fixup_rel=fixup_rel)

@@ -1,0 +1,124 @@
+"""Full-size GPU parity through the C-ABI, in the batched launch configuration
+the benchmark times.
+
+* knn-50x8000 (the benchmark workload): every output of all 400 pairs;
+* strips (500 images, 2k-20k features) and knn-200x40000: every pair matched
+  on the GPU, sampled pairs against the oracle (the largest and smallest db
+  images, so both the LDS-staged and the global-memory match paths, plus
+  random ones);
+* a grid view graph run end to end through an MBR schedule whose residency
+  cap binds (images loaded and evicted between block rows), every output
+  against the oracle.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2505_22089_amd import chm, synth
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+from tests.gpu_helpers import device, gpu_arrays, load_all, new_store, run_match  # noqa: E402
+
+
+def oracle_slices(wl, pairs):
+    """Oracle matches of the listed pairs (images hashed on demand)."""
+    ids = sorted(set(np.asarray(pairs).ravel().tolist()))
+    H = O.hash_workload(wl, ids)
+    out, offs, _, _ = O.match_pairs(H, pairs, wl.L, wl.m, wl.K, wl.ratio)
+    return [out[offs[k]:offs[k + 1]] for k in range(len(pairs))]
+
+
+def gpu_slices(out, offs, idx):
+    return [out[offs[p]:offs[p + 1]] for p in idx]
+
+
+def sample_pairs(wl, n_each, seed):
+    rng = np.random.default_rng(seed)
+    nd = np.array([wl.images[d].shape[0] for d in wl.pairs[:, 1]])
+    order = np.argsort(nd, kind="stable")
+    idx = set(order[:n_each].tolist()) | set(order[-n_each:].tolist())
+    idx |= set(rng.choice(len(wl.pairs), n_each, replace=False).tolist())
+    return sorted(idx)
+
+
+def test_knn_50x8000_all_pairs():
+    wl = synth.config2()
+    st = new_store(wl)
+    load_all(st, wl.images)
+    for i in (0, len(wl.images) - 1):
+        g = gpu_arrays(st, i)
+        ref = O.hash_image(wl.images[i], wl.W, wl.mu, wl.L, wl.m)
+        assert np.array_equal(g["codes"], ref.codes) and np.array_equal(g["members"], ref.members)
+    out, _, offs = run_match(st, wl.pairs)
+    H = O.hash_workload(wl)
+    ref, roffs, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
+    assert np.array_equal(offs, roffs)
+    assert np.array_equal(out, ref)
+    # the benchmark's tuned launch shape and the plain path agree
+    st.set_tuning(queries_per_item=2048, wg_threads=1024, lds_codes=1, grid_per_cu=1)
+    assert np.array_equal(run_match(st, wl.pairs)[0], ref)
+    st.set_tuning(wg_threads=256, lds_codes=0)
+    assert np.array_equal(run_match(st, wl.pairs, mode=chm.MATCH_PLAIN)[0], ref)
+    st.close()
+
+
+def test_strips_sampled_pairs():
+    wl = synth.config3()
+    st = new_store(wl)
+    load_all(st, wl.images)
+    nd = np.array([x.shape[0] for x in wl.images])
+    assert nd.min() < 9789 < nd.max()  # LDS-staged and global-memory db images both occur
+    out, _, offs = run_match(st, wl.pairs)
+    idx = sample_pairs(wl, 8, seed=3)
+    ref = oracle_slices(wl, wl.pairs[idx])
+    for k, (g, r) in enumerate(zip(gpu_slices(out, offs, idx), ref)):
+        assert np.array_equal(g, r), "pair %d %s" % (idx[k], wl.pairs[idx[k]])
+    st.close()
+
+
+def test_knn_200x40000_sampled_pairs():
+    wl = synth.config4()
+    st = new_store(wl)
+    load_all(st, wl.images)
+    out, _, offs = run_match(st, wl.pairs)
+    idx = sorted(np.random.default_rng(4).choice(len(wl.pairs), 3, replace=False).tolist())
+    ref = oracle_slices(wl, wl.pairs[idx])
+    for k, (g, r) in enumerate(zip(gpu_slices(out, offs, idx), ref)):
+        assert np.array_equal(g, r), "pair %d %s" % (idx[k], wl.pairs[idx[k]])
+
+    # FP32 projection gives the same codes
+    st.close()
+    del st
+    torch.cuda.empty_cache()
+    st32 = new_store(wl, chm.PROJ_FP32)
+    load_all(st32, wl.images[:2])
+    for i in (0, 1):
+        g = gpu_arrays(st32, i)
+        ref_h = O.hash_image(wl.images[i], wl.W, wl.mu, wl.L, wl.m)
+        assert np.array_equal(g["codes"], ref_h.codes) and np.array_equal(g["ids"], ref_h.ids)
+    st32.close()
+
+
+def test_grid_through_binding_mbr_schedule():
+    wl = synth.config5(rows=8, cols=30, n_feats=2000)
+    n = len(wl.images)
+    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio)
+    sizes = [chm.image_bytes(cfg, x.shape[0]) + 256 for x in wl.images]
+    cap = 40 * sizes[0]  # 40 of 240 images resident at a time
+    sched = chm.schedule_mbr(n, wl.pairs, sizes, cap, 16, keep_handle=True)
+    assert sched.iterations >= 2 and max(len(s["load"]) for s in sched.steps) > 0
+    arena = torch.empty(chm.store_overhead_bytes(cfg) + cap + (16 << 20), dtype=torch.uint8,
+                        device=device())
+    st = chm.Store(cfg, wl.W, wl.mu, arena)
+    offs = np.zeros(len(wl.pairs) + 1, np.int64)
+    offs[1:] = np.cumsum([wl.images[q].shape[0] for q in wl.pairs[:, 0]])
+    out = torch.full((int(offs[-1]),), -7, dtype=torch.int32, device=device())
+    chm.run_schedule(st, sched, wl.pairs, wl.images, offs, out)
+    torch.cuda.synchronize()
+    chm.schedule_free(sched)
+    H = O.hash_workload(wl)
+    ref, roffs, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
+    assert np.array_equal(offs, roffs)
+    assert np.array_equal(out.cpu().numpy(), ref)
+    st.close()

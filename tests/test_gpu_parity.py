@@ -12,7 +12,7 @@ from paper_2505_22089_amd import chm, synth
 pytestmark = pytest.mark.gpu
 
 torch = pytest.importorskip("torch")
-from tests.gpu_helpers import gpu_arrays, load_all, new_store, run_match  # noqa: E402
+from tests.gpu_helpers import device, gpu_arrays, load_all, new_store, run_match  # noqa: E402
 
 
 def small_workload(sizes, seed=0, L=6, m=8, K=8, copies=0.5):
@@ -130,6 +130,29 @@ def test_match_parity_config1(mode):
     out = check_matches(st, wl, [(0, 1), (1, 0), (0, 0)], mode, 2)
     gt = {int(a): int(b) for a, b in wl.gt}
     assert np.mean([out[a] == b for a, b in gt.items()]) > 0.9
+
+
+@pytest.mark.parametrize("mode", [chm.MATCH_PLAIN, chm.MATCH_BATCHED])
+def test_match_parity_arena_low_dword_above_2gib(mode):
+    """Regression: every device address of the store has its low 32 bits in
+    [2^31, 2^32), so a pointer rebuilt from two 32-bit halves in SGPRs must not
+    sign-extend the low half (it once did, and the match kernel faulted)."""
+    wl = synth.config1()
+    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio)
+    need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256
+                                               for x in wl.images) + (16 << 20)
+    assert need < (1 << 30)
+    big = torch.empty(need + (1 << 32), dtype=torch.uint8, device=device())
+    base = big.data_ptr()
+    target = ((base >> 32) << 32) + (3 << 30)  # low dword 0xC0000000
+    if target < base:
+        target += 1 << 32
+    arena = big[target - base:target - base + need]
+    assert arena.data_ptr() & 0xFFFFFFFF >= 0xC0000000
+    st = chm.Store(cfg, wl.W, wl.mu, arena)
+    load_all(st, wl.images)
+    check_matches(st, wl, [(0, 1), (1, 0)], mode, wl.K)
+    st.close()
 
 
 @pytest.mark.parametrize("K", [1, 2, 3, 8, 16, 32])
