@@ -48,8 +48,9 @@ def parse():
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-reuse", action="store_true",
                     help="also time the plain path re-hashing both images of every pair")
-    ap.add_argument("--tuning", default="auto",
-                    help="'auto' (autotuner), 'default', or queries_per_item,wg_threads,lds_codes,grid_per_cu")
+    ap.add_argument("--tuning", default="default",
+                    help="'default' (the library's), 'auto' (autotuner), or "
+                         "queries_per_item,wg_threads,lds_codes,grid_per_cu")
     return ap.parse_args()
 
 
