@@ -37,7 +37,7 @@ __device__ __forceinline__ uint64_t peers_of(uint32_t b, bool valid, int m) {
 }
 
 __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
-  __shared__ uint8_t sId[kBucketMaxN];
+  extern __shared__ uint8_t sId[];  // the table's ids (dynamic: the batch's largest n_pad)
   __shared__ uint32_t cnt[kBucketWaves][256];
   __shared__ uint32_t first[256];   // smallest member of each bucket
   __shared__ uint32_t real[256];    // members of each bucket
@@ -150,7 +150,19 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
 
 hipError_t launch_buckets(const HashBatch& hb, hipStream_t s) {
   if (hb.count == 0) return hipSuccess;
-  hipLaunchKernelGGL(k_buckets, dim3(hb.count * hb.L), dim3(kBucketWG), 0, s, hb);
+  // LDS for the ids sized to the batch, so that small images leave room for
+  // several work-groups per CU
+  int n_pad = 8;
+  for (int i = 0; i < hb.count; ++i) n_pad = max(n_pad, (hb.img[i].n + 7) / 8 * 8);
+  if (n_pad > kBucketMaxN) return hipErrorInvalidValue;
+  static bool attr_set = false;
+  if (!attr_set) {
+    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_buckets),
+                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBucketMaxN);
+    if (e != hipSuccess) return e;
+    attr_set = true;
+  }
+  hipLaunchKernelGGL(k_buckets, dim3(hb.count * hb.L), dim3(kBucketWG), (size_t)n_pad, s, hb);
   return hipGetLastError();
 }
 

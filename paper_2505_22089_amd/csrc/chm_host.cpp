@@ -114,11 +114,13 @@ void Arena::release(uint64_t off, uint64_t bytes) {
 
 static const uint64_t kHdrW = 0;
 static const uint64_t kHdrTau = round_up((uint64_t)kRowsPad * kDim * 2, 256);
-static const uint64_t kHdrCmu = kHdrTau + round_up(kRowsPad * 4, 256);
+static const uint64_t kHdrCmu = kHdrTau + round_up(3 * kRowsPad * 4, 256);
 static const uint64_t kHdrMu = kHdrCmu + round_up(kRowsPad * 8, 256);
 static const uint64_t kHdrFix = kHdrMu + 256;
 static const uint64_t kHdrFixList = kHdrFix + 256;
-static const uint64_t kHdrBytes = kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + kMaxProjWaves) * 4, 256);
+// fix-up list: overflow flag, per-wave counts, regions, then per-wave flips
+static const uint64_t kHdrBytes =
+    kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + 2 * (uint64_t)kMaxProjWaves) * 4, 256);
 
 extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
   clear_error();
@@ -167,7 +169,9 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
 
   std::vector<uint16_t> W(kRowsPad * kDim, 0);
   std::memcpy(W.data(), h_W, sizeof(uint16_t) * R * kDim);
-  std::vector<float> tau(kRowsPad, 0.f);
+  // per row: tau_r = fixup_rel ||W_r||, kappa_r = fixup_rel |c_r| (both
+  // rounded up) and c_r rounded to fp32
+  std::vector<float> tau(3 * kRowsPad, 0.f);
   std::vector<double> cmu(kRowsPad, 0.0);
   for (int r = 0; r < R; ++r) {
     double s = 0, c = 0;
@@ -179,10 +183,14 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
       c += (double)f * (double)h_mu[d];  // exact: multiples of 2^-23 below 2^21
     }
     cmu[r] = c;
-    const double t = cfg->fixup_rel * std::sqrt(s);
-    float tf = (float)t;
-    if ((double)tf < t) tf = std::nextafter(tf, INFINITY);
-    tau[r] = std::nextafter(tf, INFINITY);
+    auto up = [](double t) {
+      float tf = (float)t;
+      if ((double)tf < t) tf = std::nextafter(tf, INFINITY);
+      return std::nextafter(tf, INFINITY);
+    };
+    tau[r] = up(cfg->fixup_rel * std::sqrt(s));
+    tau[kRowsPad + r] = up(cfg->fixup_rel * std::fabs(c));
+    tau[2 * kRowsPad + r] = (float)c;
   }
 
   chm_store* S = new chm_store();
@@ -250,6 +258,7 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
   pc.fixups = S->dFix;
   pc.fixlist = S->dFixList;
   pc.fix_cap = kFixListCap;
+  pc.fixflips = S->dFixList + 1 + kMaxProjWaves + kFixListCap;
   pc.R = S->R;
   for (size_t i0 = 0; i0 < slots.size();) {
     HashBatch hb;
@@ -453,11 +462,13 @@ extern "C" chm_status chm_store_set_tuning(chm_store* S, const chm_tuning* t) {
 
 // ------------------------------------------------------------------ plans
 
-static const int kLdsBudget = 160 * 1024 - 1024;
+static const size_t kLdsBudget = 160 * 1024 - 1024;  // a CU's LDS less a reserve
 
+// Codes the match kernel can stage in LDS: what is left of a CU's LDS after
+// the bucket offsets and the kernel's control words and sort arrays.
 int chm::lds_max_feats(const chm_store* S) {
-  const size_t off = (size_t)S->cfg.num_tables * (S->nb + 1) * 4;
-  return (int)((kLdsBudget - (int)off) / 16);
+  const size_t off = ((size_t)S->cfg.num_tables * (S->nb + 1) + 3) / 4 * 16;
+  return (int)((kLdsBudget - off - kMatchLdsTail) / 16);
 }
 
 static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {

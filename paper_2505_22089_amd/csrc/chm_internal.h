@@ -43,6 +43,12 @@ struct WorkItem {
 // has its own L2): bin b holds items[bin_begin[b] .. bin_begin[b+1]).
 constexpr int kMaxBins = 16;
 
+// Items of at most kSortMax queries are processed in order of walk length.
+// LDS after the staged codes and offsets: two control words (16 B), the
+// sort's histogram (256 u32), order (u16) and lengths (u8).
+constexpr int kSortMax = 2048;
+constexpr size_t kMatchLdsTail = 16 + 256 * 4 + kSortMax * 3;
+
 struct MatchArgs {
   const PairDev* pairs;
   const WorkItem* items;
@@ -140,12 +146,14 @@ __host__ __device__ inline HashImage hash_image(const HashSlot& s, int L, int m)
 
 struct ProjConsts {
   const uint16_t* W;        // kRowsPad x 128 bf16 bits (rows >= R are zero)
-  const float* tau;         // kRowsPad: fixup_rel * ||W_r|| (rounded up), 0 for padding
+  const float* tau;         // 3 x kRowsPad: fixup_rel ||W_r||, fixup_rel |c_r| (both rounded
+                            // up), c_r rounded to fp32; 0 for padding rows
   const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
   unsigned long long* fixups;  // running counts: [0] fp64 recomputes, [1] bits they changed
   uint32_t* fixlist;        // [0] overflow flag, [1..n_waves] per-wave counts, then
                             // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d)
+  uint32_t* fixflips;       // kMaxProjWaves: bits each k_fixup wavefront changed
   uint32_t fix_cap;         // entries the list holds
   int32_t n_waves;          // projection wavefronts of the launch (set by launch_project)
   int32_t R;                // 128 + L*m

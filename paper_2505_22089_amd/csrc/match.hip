@@ -251,18 +251,75 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   a.out[o] = pass ? j1 : -1;
 }
 
+// LDS of the per-item query sort: order (u16), walk length (u8), histogram.
+struct SortLds {
+  uint16_t* order;
+  uint8_t* len;
+  uint32_t* hist;
+};
+
+// Orders the item's queries by their walk length (aligned blocks over the
+// L buckets, clamped to 255), longest first, so that the 64 lanes of a
+// wavefront walk about as many blocks each.  Equal lengths come in any
+// order: every query's result is independent of who computes it and when.
+template <int WG>
+__device__ __forceinline__ void sort_item(const MatchArgs& a, const PairDev& P, const WorkItem& w,
+                                          const int32_t* offs, const SortLds& s) {
+  const int nq = w.q1 - w.q0, stride = a.nb + 1;
+  for (int i = threadIdx.x; i < 256; i += WG) s.hist[i] = 0;
+  __syncthreads();
+  for (int i = threadIdx.x; i < nq; i += WG) {
+    const int q = w.q0 + i;
+    int len = 0;
+    for (int t = 0; t < a.L; ++t) {
+      const int b = *(gcu8*)(P.q.ids + (size_t)t * P.q.n_pad + q);
+      len += (offs[t * stride + b + 1] - offs[t * stride + b]) >> 3;
+    }
+    len = 255 - min(len, 255);  // descending walk length
+    s.len[i] = (uint8_t)len;
+    atomicAdd(&s.hist[len], 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < 64) {  // exclusive scan, 4 bins per lane
+    const int lane = threadIdx.x;
+    uint32_t v[4], run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      v[k] = s.hist[4 * lane + k];
+      run += v[k];
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(incl, d);
+      if (lane >= d) incl += u;
+    }
+    uint32_t base = incl - run;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      s.hist[4 * lane + k] = base;
+      base += v[k];
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < nq; i += WG) s.order[atomicAdd(&s.hist[s.len[i]], 1u)] = (uint16_t)i;
+  __syncthreads();
+}
+
 template <int KT, bool LDSC, int WG>
 __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, const WorkItem& w,
-                                         const int32_t* offs, int* s_chunk) {
+                                         const int32_t* offs, int* s_chunk, const SortLds& s) {
+  const bool sorted = w.q1 - w.q0 <= kSortMax;
+  if (sorted) sort_item<WG>(a, P, w, offs, s);
   // Wavefronts take 64-query chunks of the item in turn.
   const int lane = __lane_id();
   for (;;) {
     int c = 0;
     if (lane == 0) c = atomicAdd(s_chunk, 64);
     c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));  // uniform across the wave
-    const int q = w.q0 + c + lane;
     if (w.q0 + c >= w.q1) break;
-    if (q < w.q1) match_query<KT, LDSC>(a, P, q, offs);
+    const int i = c + lane;
+    if (w.q0 + i < w.q1) match_query<KT, LDSC>(a, P, w.q0 + (sorted ? (int)s.order[i] : i), offs);
   }
 }
 
@@ -278,6 +335,10 @@ __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
   int* sCtl = reinterpret_cast<int*>(smem + ncodes + (noffs + 3) / 4);
   int& s_item = sCtl[0];
   int& s_chunk = sCtl[1];
+  SortLds sl;
+  sl.hist = reinterpret_cast<uint32_t*>(sCtl + 4);
+  sl.order = reinterpret_cast<uint16_t*>(sl.hist + 256);
+  sl.len = reinterpret_cast<uint8_t*>(sl.order + kSortMax);
   const uint4* staged = nullptr;
   int it = PERSIST ? 0 : a.item_base + (int)blockIdx.x;
   // Persistent: start with the bin of this work-group's XCD (work-groups
@@ -319,9 +380,9 @@ __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
     }
     __syncthreads();
     if (use_lds)
-      run_item<KT, true, WG>(a, P, w, sOffs, &s_chunk);
+      run_item<KT, true, WG>(a, P, w, sOffs, &s_chunk, sl);
     else
-      run_item<KT, false, WG>(a, P, w, P.d.offsets, &s_chunk);
+      run_item<KT, false, WG>(a, P, w, P.d.offsets, &s_chunk, sl);
     __syncthreads();
     if (!PERSIST) break;
   }
@@ -329,12 +390,12 @@ __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
 
 size_t match_lds_bytes(int lds_max_feats, int L, int nb) {
   const size_t offs = ((size_t)L * (nb + 1) + 3) / 4 * sizeof(uint4);
-  return (size_t)lds_max_feats * sizeof(uint4) + offs + sizeof(uint4);  // + the two control words
+  return (size_t)lds_max_feats * sizeof(uint4) + offs + kMatchLdsTail;
 }
 
 template <int KT, int WG, bool LDSC, bool PERSIST>
 static hipError_t launch_one(const MatchArgs& a, int grid, hipStream_t s) {
-  const size_t lds = LDSC ? match_lds_bytes(a.lds_max_feats, a.L, a.nb) : sizeof(uint4);
+  const size_t lds = LDSC ? match_lds_bytes(a.lds_max_feats, a.L, a.nb) : kMatchLdsTail;
   auto fn = k_match<KT, WG, LDSC, PERSIST>;
   static int static_lds = -1;  // the code stage must start at LDS address 0
   if (static_lds < 0) {
@@ -344,7 +405,7 @@ static hipError_t launch_one(const MatchArgs& a, int grid, hipStream_t s) {
     static_lds = (int)attr.sharedSizeBytes;
   }
   if (static_lds != 0) return hipErrorInvalidKernelFile;
-  if (LDSC) {
+  {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
     if (e != hipSuccess) return e;

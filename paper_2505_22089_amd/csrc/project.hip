@@ -1,22 +1,26 @@
 // Long codes and bucket ids (Sec. 2.3.1 steps (1)-(2)): the sign of the
-// projection p_r(x) = sum_d W[r][d] (x_d - mu_d) of every descriptor onto
-// every random row r, as an MFMA GEMM per 32-descriptor tile.
+// projection p_r(x) = sum_d W[r][d] (x_d - mu_d) = W_r . x - c_r of every
+// descriptor onto every random row r, as an MFMA GEMM per 32-descriptor
+// tile (c_r = W_r . mu is exact on the host).
 //
-// Exactness: x_d - mu_d is an integer in [-255, 255] and W is bfloat16, so
-// both MFMA input types (bf16 and fp32) hold the operands exactly and every
-// product is exact in fp32; only the fp32 accumulation rounds.  Its error is
-// below ~128 * 2^-24 * ||W_r|| ||x - mu|| (Cauchy-Schwarz), far below the
-// threshold tau_r * ||x - mu|| with tau_r = fixup_rel * ||W_r|| (1e-3 by
-// default).  Projections under the threshold are listed and recomputed in
-// fp64 by k_fixup, which is exact for these operands, so every bit equals the
-// sign of the exact value.
+// Exactness: x_d is an integer in [0, 255] and W is bfloat16, so both MFMA
+// input types (bf16 and fp32) hold the operands exactly and every product is
+// exact in fp32; only the fp32 accumulation of W_r . x and the subtraction of
+// c_r (rounded to fp32) round.  In any summation order the error is below
+// 127 * 2^-24 * (||W_r|| ||x|| + |c_r|) (Cauchy-Schwarz), twice that if the
+// accumulator truncates, well under the threshold
+// tau_r ||x|| + kappa_r = fixup_rel (||W_r|| ||x|| + |c_r|) for
+// fixup_rel >= 1e-4.  Projections under the threshold are listed and
+// recomputed in fp64 by k_fixup, which is exact for these operands, so every
+// bit equals the sign of the exact value (a zero projection gives 0).
 //
 // k_project: one work-group of kProjWaves wavefronts shares W in LDS; each
-// wavefront loops over 32-descriptor tiles.  The 192 (padded) rows are done
-// in two passes of three 32x32 output blocks.  Codes and bucket ids are
-// written from the fp32 signs; each wavefront writes the borderline
-// (descriptor, row) entries of its tiles into its own region of the global
-// fix-up list, without atomics.
+// wavefront loops over 32-descriptor tiles.  A lane's share of the tile is
+// converted to MFMA operands once (byte -> float conversions); the 192
+// (padded) rows are done in two passes of three 32x32 output blocks.  Codes
+// and bucket ids are written from the signs; each wavefront writes the
+// borderline (descriptor, row) entries of its tiles into its own region of
+// the global fix-up list, without atomics.
 // k_fixup: wavefronts walk the regions; each lane recomputes one entry
 // exactly in fp64 and patches its bit with a 32-bit atomic.  If a region
 // overflowed (adversarial inputs only), k_fixup_all instead rebuilds every
@@ -51,13 +55,20 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// bf16 patterns of bytes 2i and 2i+1 of w (integers 0..255 are exact in
+// bf16: the upper half of their fp32 pattern), packed low | high.
+__device__ __forceinline__ uint32_t bf16x2_of_bytes(uint32_t w, int i) {
+  const float lo = (float)((w >> (16 * i)) & 0xFFu);
+  const float hi = (float)((w >> (16 * i + 8)) & 0xFFu);
+  return (__float_as_uint(lo) >> 16) | (__float_as_uint(hi) & 0xFFFF0000u);
+}
+
 template <bool FP32>
 __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc) {
   __shared__ uint16_t sW[kRowsPad * kWStride];
   __shared__ uint32_t sWords[kProjWaves][32 * 6];
-  __shared__ float sTau[kRowsPad];
-  __shared__ float sSd[kProjWaves][32];   // ||x - mu|| of the wave's tile rows
-  __shared__ uint8_t sMu[kDim];
+  __shared__ float sRow[3][kRowsPad];     // tau_r, kappa_r, c_r (fp32)
+  __shared__ float sSx[kProjWaves][32];   // ||x|| (rounded up) of the wave's tile rows
 
   const int tid = threadIdx.x;
   for (int c = tid; c < kRowsPad * (kDim / 8); c += kProjWG) {
@@ -66,8 +77,7 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
     uint32_t* dst = reinterpret_cast<uint32_t*>(sW + r * kWStride + k8 * 8);
     dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
   }
-  if (tid < kDim) sMu[tid] = pc.mu[tid];
-  if (tid < kRowsPad) sTau[tid] = pc.tau[tid];
+  for (int i = tid; i < 3 * kRowsPad; i += kProjWG) (&sRow[0][0])[i] = pc.tau[i];
   __syncthreads();
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps tile / image in SGPRs
@@ -97,48 +107,44 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
     const bool valid = dr < I.n;
     const uint8_t* xrow = I.desc + (size_t)(valid ? dr : d0) * kDim;
 
-    // Raw bytes of the lane's descriptor (bf16: k = 16*kb + 8*half .. +7;
-    // fp32: the whole row), converted to MFMA operands in each pass.
-    uint32_t nx = 0, nc = 0;
-    u32x2 rawb[8];
+    // The lane's bytes of its descriptor (bf16: k = 16*kb + 8*half .. +7;
+    // fp32: the whole row); invalid rows read as zero.  ||x||^2 with dot4.
+    uint32_t nx = 0;
+    u32x4 abf[8];   // bf16 operands, converted once per tile
     u32x4 rawf[8];
     if (!FP32) {
 #pragma unroll
-      for (int kb = 0; kb < 8; ++kb)
-        rawb[kb] = valid ? *(gcu32x2*)(xrow + 16 * kb + 8 * half) : u32x2{0u, 0u};
-#pragma unroll
       for (int kb = 0; kb < 8; ++kb) {
-        const int k0 = 16 * kb + 8 * half;
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int x = (rawb[kb][q >> 2] >> (8 * (q & 3))) & 0xFF;
-          const int c = valid ? x - (int)sMu[k0 + q] : 0;
-          nx += (uint32_t)(x * x);
-          nc += (uint32_t)(c * c);
-        }
+        const u32x2 w = valid ? *(gcu32x2*)(xrow + 16 * kb + 8 * half) : u32x2{0u, 0u};
+        nx = __builtin_amdgcn_udot4(w[0], w[0], nx, false);
+        nx = __builtin_amdgcn_udot4(w[1], w[1], nx, false);
+        abf[kb] = u32x4{bf16x2_of_bytes(w[0], 0), bf16x2_of_bytes(w[0], 1), bf16x2_of_bytes(w[1], 0),
+                        bf16x2_of_bytes(w[1], 1)};
       }
+      nx += __shfl_xor(nx, 32);
     } else {
 #pragma unroll
-      for (int q = 0; q < 8; ++q) rawf[q] = valid ? *(gcu32x4*)(xrow + 16 * q) : u32x4{0u, 0u, 0u, 0u};
+      for (int q = 0; q < 8; ++q) {
+        rawf[q] = valid ? *(gcu32x4*)(xrow + 16 * q) : u32x4{0u, 0u, 0u, 0u};
 #pragma unroll
-      for (int kk = 0; kk < 64; ++kk) {
-        const int k = 2 * kk + half;
-        const int x = (rawf[kk >> 3][(kk >> 1) & 3] >> (8 * (k & 3))) & 0xFF;
-        const int c = valid ? x - (int)sMu[k] : 0;
-        nx += (uint32_t)(x * x);
-        nc += (uint32_t)(c * c);
+        for (int j = 0; j < 4; ++j) nx = __builtin_amdgcn_udot4(rawf[q][j], rawf[q][j], nx, false);
       }
     }
-    nx += __shfl_xor(nx, 32);
-    nc += __shfl_xor(nc, 32);
-    if (lane < 32) sSd[wave][lane] = valid ? sqrtf((float)nc) * 1.000001f : 0.f;
+    if (lane < 32) sSx[wave][lane] = valid ? sqrtf((float)nx) * 1.000001f : 0.f;
     wave_sync();
 
-    // per lane, borderline accumulator elements: bit 16*(blk&1) + e of bm3[blk>>1]
-    uint32_t bm3[3] = {0u, 0u, 0u};
+    // per lane, borderline accumulator elements: block b of pass p sets bit
+    // 16*b + e of bmA[p] (b < 2) or bit e of bmB[p] (b = 2)
+    uint32_t bmA[2] = {0u, 0u}, bmB[2] = {0u, 0u};
+    // elements whose descriptor (8*(e/4) + 4*half + e%4 of the tile) exists
+    uint32_t vm = 0;
 #pragma unroll
+    for (int e = 0; e < 16; ++e) vm |= (d0 + 8 * (e >> 2) + 4 * half + (e & 3) < I.n) ? (1u << e) : 0u;
+    vm |= vm << 16;
+#pragma unroll 1
     for (int pass = 0; pass < 2; ++pass) {
       f32x16 acc[3];
+      uint32_t ma = 0u, mb = 0u;
 #pragma unroll
       for (int b = 0; b < 3; ++b)
 #pragma unroll
@@ -147,18 +153,7 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const int k0 = 16 * kb + 8 * half;
-          const uint2 mu8 = *reinterpret_cast<const uint2*>(sMu + k0);
-          u32x4 a;
-#pragma unroll
-          for (int p = 0; p < 4; ++p) {
-            const uint32_t w = rawb[kb][p >> 1];
-            const uint32_t m = p < 2 ? mu8.x : mu8.y;
-            const int s0 = (p & 1) * 16;
-            const int c0 = valid ? (int)((w >> s0) & 0xFF) - (int)((m >> s0) & 0xFF) : 0;
-            const int c1 = valid ? (int)((w >> (s0 + 8)) & 0xFF) - (int)((m >> (s0 + 8)) & 0xFF) : 0;
-            a[p] = bf16_bits_of_int(c0) | (bf16_bits_of_int(c1) << 16);
-          }
-          const bf16x8 Ab = __builtin_bit_cast(bf16x8, a);
+          const bf16x8 Ab = __builtin_bit_cast(bf16x8, abf[kb]);
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             const int row = 32 * (3 * pass + b) + col;
@@ -171,8 +166,7 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
 #pragma unroll
         for (int kk = 0; kk < 64; ++kk) {
           const int k = 2 * kk + half;
-          const int x = (rawf[kk >> 3][(kk >> 1) & 3] >> (8 * (k & 3))) & 0xFF;
-          const float Af = valid ? (float)(x - (int)sMu[k]) : 0.f;
+          const float Af = (float)((rawf[kk >> 3][(kk >> 1) & 3] >> (8 * (k & 3))) & 0xFFu);
 #pragma unroll
           for (int b = 0; b < 3; ++b) {
             const int row = 32 * (3 * pass + b) + col;
@@ -184,29 +178,40 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
 #pragma unroll
       for (int b = 0; b < 3; ++b) {
         const int blk = 3 * pass + b;
-        const float tau = sTau[32 * blk + col];
+        const float tau = sRow[0][32 * blk + col], kap = sRow[1][32 * blk + col];
+        const float cr = sRow[2][32 * blk + col];
         uint32_t word = 0;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           // descriptors 8q + 4*half + 0..3 of the tile
-          const float4 sd4 = *reinterpret_cast<const float4*>(&sSd[wave][8 * q + 4 * half]);
-          const float th[4] = {tau * sd4.x, tau * sd4.y, tau * sd4.z, tau * sd4.w};
+          const float4 sx4 = *reinterpret_cast<const float4*>(&sSx[wave][8 * q + 4 * half]);
+          const float sx[4] = {sx4.x, sx4.y, sx4.z, sx4.w};
 #pragma unroll
           for (int i = 0; i < 4; ++i) {
             const int e = 4 * q + i;
-            const float v = acc[b][e];
+            const float v = acc[b][e] - cr;
             const uint64_t bits = __ballot(v > 0.f);
             if (e == eL) word = hiL ? (uint32_t)(bits >> 32) : (uint32_t)bits;
-            bm3[blk >> 1] |= (fabsf(v) < th[i]) ? (1u << (16 * (blk & 1) + e)) : 0u;
+            const bool border = fabsf(v) < fmaf(tau, sx[i], kap);
+            if (b < 2) ma |= border ? (1u << (16 * b + e)) : 0u;
+            else mb |= border ? (1u << e) : 0u;
           }
         }
         if (lane < 32) words[lane * 6 + blk] = word;
+      }
+      if (pass == 0) {
+        bmA[0] = ma;
+        bmB[0] = mb;
+      } else {
+        bmA[1] = ma;
+        bmB[1] = mb;
       }
     }
     // Borderline entries of the tile go straight to this wavefront's region of
     // the global list (no atomics): lane offsets from a wave prefix sum.
     {
-      const int mine = __popc(bm3[0]) + __popc(bm3[1]) + __popc(bm3[2]);
+      const uint32_t bm4[4] = {bmA[0] & vm, bmB[0] & vm, bmA[1] & vm, bmB[1] & vm};
+      const int mine = __popc(bm4[0]) + __popc(bm4[1]) + __popc(bm4[2]) + __popc(bm4[3]);
       int incl = mine;
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
@@ -216,12 +221,12 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
       const uint32_t tile_n = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
       uint32_t idx = wcount + (uint32_t)(incl - mine);
 #pragma unroll
-      for (int w3 = 0; w3 < 3; ++w3) {
-        uint32_t m = bm3[w3];
+      for (int w4 = 0; w4 < 4; ++w4) {
+        uint32_t m = bm4[w4];
         while (m) {
           const int bit = __builtin_ctz(m);
           m &= m - 1u;
-          const int blk = 2 * w3 + (bit >> 4), e = bit & 15;
+          const int blk = 3 * (w4 >> 1) + ((w4 & 1) ? 2 : (bit >> 4)), e = bit & 15;
           const int drel = 8 * (e >> 2) + 4 * half + (e & 3);
           if (idx < cap_w)
             region[idx] = ((uint32_t)im << 24) | ((uint32_t)(32 * blk + col) << 16) | (uint32_t)(d0 + drel);
@@ -303,10 +308,12 @@ __device__ __forceinline__ double exact_projection_lds(const uint8_t* xr, const 
 constexpr int kFixWG = 512;
 
 __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
-  __shared__ uint16_t sW[kRowsPad * kDim];
+  __shared__ uint16_t sW[kRowsPad * kWStride];
   if (pc.fixlist[0] != 0) return;  // overflow: k_fixup_all rebuilds the batch
-  for (int c = threadIdx.x; c < kRowsPad * kDim / 8; c += kFixWG)
-    reinterpret_cast<uint4*>(sW)[c] = reinterpret_cast<const uint4*>(pc.W)[c];
+  for (int c = threadIdx.x; c < kRowsPad * kDim / 8; c += kFixWG) {
+    const int r = c / (kDim / 8), k8 = c % (kDim / 8);
+    *reinterpret_cast<uint4*>(sW + r * kWStride + 8 * k8) = reinterpret_cast<const uint4*>(pc.W)[c];
+  }
   __syncthreads();
   const uint32_t cap_w = pc.fix_cap / pc.n_waves;
   const uint32_t* counts = pc.fixlist + 1;
@@ -315,14 +322,14 @@ __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
   // a wavefront takes whole regions; its lanes stride inside one
   const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kFixWG / 64) + (threadIdx.x >> 6)));
   const int nw = gridDim.x * (kFixWG / 64);
-  uint32_t done = 0, flips = 0;
+  uint32_t flips = 0;
   for (int r = wid; r < pc.n_waves; r += nw) {
     const uint32_t count = counts[r];
     for (uint32_t k = lane; k < count; k += 64) {
       const uint32_t ent = entries[(size_t)r * cap_w + k];
       const int im = ent >> 24, row = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
       const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
-      const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kDim, pc.cmu[row]);
+      const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kWStride, pc.cmu[row]);
       bool changed;
       if (row < 128) {
         changed = set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
@@ -334,10 +341,28 @@ __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
       }
       flips += __popcll(__ballot(changed));
     }
-    done += count;
   }
-  if (lane == 0 && done) atomicAdd(pc.fixups, (unsigned long long)done);
-  if (lane == 0 && flips) atomicAdd(pc.fixups + 1, (unsigned long long)flips);
+  // per-wavefront slot, summed by k_fix_count (no contended atomics)
+  if (lane == 0) pc.fixflips[wid] = flips;
+}
+
+// Adds the batch's fix-up count (the region counts) and changed bits (the
+// k_fixup slots) to the store's running counters.
+__global__ __launch_bounds__(1024) void k_fix_count(ProjConsts pc, int n_fix_waves) {
+  __shared__ unsigned long long s_sum[2];
+  if (pc.fixlist[0] != 0) return;  // overflow: k_fixup_all counts instead
+  if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
+  __syncthreads();
+  unsigned long long a = 0, b = 0;
+  for (int i = threadIdx.x; i < pc.n_waves; i += 1024) a += pc.fixlist[1 + i];
+  for (int i = threadIdx.x; i < n_fix_waves; i += 1024) b += pc.fixflips[i];
+  if (a) atomicAdd(&s_sum[0], a);
+  if (b) atomicAdd(&s_sum[1], b);
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    if (s_sum[0]) atomicAdd(pc.fixups, s_sum[0]);
+    if (s_sum[1]) atomicAdd(pc.fixups + 1, s_sum[1]);
+  }
 }
 
 // After an overflow of the fix-up list: rebuild every code and bucket id of
@@ -394,7 +419,10 @@ hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, i
     hipLaunchKernelGGL(k_project<false>, dim3(grid), dim3(kProjWG), 0, s, hb, p2);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_fixup, dim3(2 * n_cu), dim3(kFixWG), 0, s, hb, p2);
+  int fgrid = 2 * n_cu;
+  if (fgrid * (kFixWG / 64) > kMaxProjWaves) fgrid = kMaxProjWaves / (kFixWG / 64);
+  hipLaunchKernelGGL(k_fixup, dim3(fgrid), dim3(kFixWG), 0, s, hb, p2);
+  hipLaunchKernelGGL(k_fix_count, dim3(1), dim3(1024), 0, s, p2, fgrid * (kFixWG / 64));
   hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, p2);
   return hipGetLastError();
 }
