@@ -64,15 +64,15 @@ typedef struct chm_config {
   int32_t ratio_den;
   int32_t proj_precision; /* CHM_PROJ_BF16 or CHM_PROJ_FP32 (MFMA input type) */
   int32_t reserved;       /* must be 0 */
-  double fixup_rel;       /* a projection p is recomputed in fp64 when
-                             |p| < fixup_rel * ||W_r||_2 * ||x - mu||_2;
+  double fixup_rel;       /* a projection p_r(x) = W_r.x - c_r (c_r = W_r.mu) is
+                             recomputed in fp64 when its fp32 value v has
+                             |v| < fixup_rel * (||W_r||_2 * ||x||_2 + |c_r|);
                              must lie in [1e-4, 0.5].  The fp32 sum of the
-                             128 exact products errs by at most
-                             127 * 2^-24 * sum|W_rd (x_d - mu_d)|
-                             <= 7.6e-6 * ||W_r||_2 * ||x - mu||_2 (twice that
-                             if the accumulator truncated), so every value
-                             in the range keeps every bit exact; 1e-4 (the
-                             default) recomputes the fewest */
+                             128 exact products minus c_r errs by at most
+                             127 * 2^-24 * (||W_r||_2 ||x||_2 + |c_r|) (twice
+                             that if the accumulator truncated), so every
+                             value in the range keeps every bit exact; 1e-4
+                             (the default) recomputes the fewest */
 } chm_config;
 
 /* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-4). */

@@ -64,7 +64,7 @@ __device__ __forceinline__ uint32_t bf16x2_of_bytes(uint32_t w, int i) {
 }
 
 template <bool FP32>
-__global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc) {
+__global__ __launch_bounds__(kProjWG, FP32 ? 2 : 3) void k_project(HashBatch hb, ProjConsts pc) {
   __shared__ uint16_t sW[kRowsPad * kWStride];
   __shared__ uint32_t sWords[kProjWaves][32 * 6];
   __shared__ float sRow[3][kRowsPad];     // tau_r, kappa_r, c_r (fp32)
@@ -133,85 +133,66 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
     if (lane < 32) sSx[wave][lane] = valid ? sqrtf((float)nx) * 1.000001f : 0.f;
     wave_sync();
 
-    // per lane, borderline accumulator elements: block b of pass p sets bit
-    // 16*b + e of bmA[p] (b < 2) or bit e of bmB[p] (b = 2)
-    uint32_t bmA[2] = {0u, 0u}, bmB[2] = {0u, 0u};
+    // per lane, borderline accumulator elements: bit 16*(blk&1) + e of bm3[blk>>1]
+    uint32_t bm3[3] = {0u, 0u, 0u};
     // elements whose descriptor (8*(e/4) + 4*half + e%4 of the tile) exists
     uint32_t vm = 0;
 #pragma unroll
     for (int e = 0; e < 16; ++e) vm |= (d0 + 8 * (e >> 2) + 4 * half + (e & 3) < I.n) ? (1u << e) : 0u;
     vm |= vm << 16;
+    // One 32x32 block of rows at a time: a single accumulator keeps the
+    // register count low enough for four wavefronts per SIMD.
 #pragma unroll 1
-    for (int pass = 0; pass < 2; ++pass) {
-      f32x16 acc[3];
-      uint32_t ma = 0u, mb = 0u;
+    for (int blk = 0; blk < 6; ++blk) {
+      f32x16 acc;
 #pragma unroll
-      for (int b = 0; b < 3; ++b)
-#pragma unroll
-        for (int e = 0; e < 16; ++e) acc[b][e] = 0.f;
+      for (int e = 0; e < 16; ++e) acc[e] = 0.f;
+      const int row = 32 * blk + col;
       if (!FP32) {
 #pragma unroll
         for (int kb = 0; kb < 8; ++kb) {
           const int k0 = 16 * kb + 8 * half;
-          const bf16x8 Ab = __builtin_bit_cast(bf16x8, abf[kb]);
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int row = 32 * (3 * pass + b) + col;
-            const u32x4 bw = *reinterpret_cast<const u32x4*>(sW + row * kWStride + k0);
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(Ab, __builtin_bit_cast(bf16x8, bw),
-                                                            acc[b], 0, 0, 0);
-          }
+          const u32x4 bw = *reinterpret_cast<const u32x4*>(sW + row * kWStride + k0);
+          acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, abf[kb]),
+                                                        __builtin_bit_cast(bf16x8, bw), acc, 0, 0, 0);
         }
       } else {
 #pragma unroll
         for (int kk = 0; kk < 64; ++kk) {
           const int k = 2 * kk + half;
           const float Af = (float)((rawf[kk >> 3][(kk >> 1) & 3] >> (8 * (k & 3))) & 0xFFu);
-#pragma unroll
-          for (int b = 0; b < 3; ++b) {
-            const int row = 32 * (3 * pass + b) + col;
-            acc[b] = __builtin_amdgcn_mfma_f32_32x32x2f32(Af, bf16_to_f32(sW[row * kWStride + k]),
-                                                         acc[b], 0, 0, 0);
-          }
+          acc = __builtin_amdgcn_mfma_f32_32x32x2f32(Af, bf16_to_f32(sW[row * kWStride + k]), acc, 0, 0, 0);
         }
       }
+      const float tau = sRow[0][row], kap = sRow[1][row], cr = sRow[2][row];
+      uint32_t word = 0, m = 0;
 #pragma unroll
-      for (int b = 0; b < 3; ++b) {
-        const int blk = 3 * pass + b;
-        const float tau = sRow[0][32 * blk + col], kap = sRow[1][32 * blk + col];
-        const float cr = sRow[2][32 * blk + col];
-        uint32_t word = 0;
+      for (int q = 0; q < 4; ++q) {
+        // descriptors 8q + 4*half + 0..3 of the tile
+        const float4 sx4 = *reinterpret_cast<const float4*>(&sSx[wave][8 * q + 4 * half]);
+        const float sx[4] = {sx4.x, sx4.y, sx4.z, sx4.w};
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          // descriptors 8q + 4*half + 0..3 of the tile
-          const float4 sx4 = *reinterpret_cast<const float4*>(&sSx[wave][8 * q + 4 * half]);
-          const float sx[4] = {sx4.x, sx4.y, sx4.z, sx4.w};
-#pragma unroll
-          for (int i = 0; i < 4; ++i) {
-            const int e = 4 * q + i;
-            const float v = acc[b][e] - cr;
-            const uint64_t bits = __ballot(v > 0.f);
-            if (e == eL) word = hiL ? (uint32_t)(bits >> 32) : (uint32_t)bits;
-            const bool border = fabsf(v) < fmaf(tau, sx[i], kap);
-            if (b < 2) ma |= border ? (1u << (16 * b + e)) : 0u;
-            else mb |= border ? (1u << e) : 0u;
-          }
+        for (int i = 0; i < 4; ++i) {
+          const int e = 4 * q + i;
+          const float v = acc[e] - cr;
+          const uint64_t bits = __ballot(v > 0.f);
+          if (e == eL) word = hiL ? (uint32_t)(bits >> 32) : (uint32_t)bits;
+          m |= (fabsf(v) < fmaf(tau, sx[i], kap)) ? (1u << e) : 0u;
         }
-        if (lane < 32) words[lane * 6 + blk] = word;
       }
-      if (pass == 0) {
-        bmA[0] = ma;
-        bmB[0] = mb;
-      } else {
-        bmA[1] = ma;
-        bmB[1] = mb;
-      }
+      if (lane < 32) words[lane * 6 + blk] = word;
+      m <<= 16 * (blk & 1);
+      if (blk < 2) bm3[0] |= m;
+      else if (blk < 4) bm3[1] |= m;
+      else bm3[2] |= m;
     }
     // Borderline entries of the tile go straight to this wavefront's region of
     // the global list (no atomics): lane offsets from a wave prefix sum.
     {
-      const uint32_t bm4[4] = {bmA[0] & vm, bmB[0] & vm, bmA[1] & vm, bmB[1] & vm};
-      const int mine = __popc(bm4[0]) + __popc(bm4[1]) + __popc(bm4[2]) + __popc(bm4[3]);
+      bm3[0] &= vm;
+      bm3[1] &= vm;
+      bm3[2] &= vm;
+      const int mine = __popc(bm3[0]) + __popc(bm3[1]) + __popc(bm3[2]);
       int incl = mine;
 #pragma unroll
       for (int d = 1; d < 64; d <<= 1) {
@@ -221,12 +202,12 @@ __global__ __launch_bounds__(kProjWG) void k_project(HashBatch hb, ProjConsts pc
       const uint32_t tile_n = __builtin_amdgcn_readfirstlane(__shfl(incl, 63));
       uint32_t idx = wcount + (uint32_t)(incl - mine);
 #pragma unroll
-      for (int w4 = 0; w4 < 4; ++w4) {
-        uint32_t m = bm4[w4];
+      for (int w3 = 0; w3 < 3; ++w3) {
+        uint32_t m = bm3[w3];
         while (m) {
           const int bit = __builtin_ctz(m);
           m &= m - 1u;
-          const int blk = 3 * (w4 >> 1) + ((w4 & 1) ? 2 : (bit >> 4)), e = bit & 15;
+          const int blk = 2 * w3 + (bit >> 4), e = bit & 15;
           const int drel = 8 * (e >> 2) + 4 * half + (e & 3);
           if (idx < cap_w)
             region[idx] = ((uint32_t)im << 24) | ((uint32_t)(32 * blk + col) << 16) | (uint32_t)(d0 + drel);
@@ -342,20 +323,19 @@ __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
       flips += __popcll(__ballot(changed));
     }
   }
-  // per-wavefront slot, summed by k_fix_count (no contended atomics)
+  // per-wavefront slot, summed by k_fixup_all (no contended atomics)
   if (lane == 0) pc.fixflips[wid] = flips;
 }
 
-// Adds the batch's fix-up count (the region counts) and changed bits (the
-// k_fixup slots) to the store's running counters.
-__global__ __launch_bounds__(1024) void k_fix_count(ProjConsts pc, int n_fix_waves) {
+// Sums the batch's fix-up count (the region counts) and changed bits (the
+// k_fixup slots) into the store's running counters.
+__device__ void fix_count(const ProjConsts& pc, int n_fix_waves) {
   __shared__ unsigned long long s_sum[2];
-  if (pc.fixlist[0] != 0) return;  // overflow: k_fixup_all counts instead
   if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long a = 0, b = 0;
-  for (int i = threadIdx.x; i < pc.n_waves; i += 1024) a += pc.fixlist[1 + i];
-  for (int i = threadIdx.x; i < n_fix_waves; i += 1024) b += pc.fixflips[i];
+  for (int i = threadIdx.x; i < pc.n_waves; i += blockDim.x) a += pc.fixlist[1 + i];
+  for (int i = threadIdx.x; i < n_fix_waves; i += blockDim.x) b += pc.fixflips[i];
   if (a) atomicAdd(&s_sum[0], a);
   if (b) atomicAdd(&s_sum[1], b);
   __syncthreads();
@@ -365,10 +345,14 @@ __global__ __launch_bounds__(1024) void k_fix_count(ProjConsts pc, int n_fix_wav
   }
 }
 
-// After an overflow of the fix-up list: rebuild every code and bucket id of
+// Without an overflow of the fix-up list, work-group 0 only counts.  After
+// one, every work-group rebuilds its share of the codes and bucket ids of
 // the batch from exact values (adversarial inputs only).
-__global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc) {
-  if (pc.fixlist[0] == 0) return;
+__global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc, int n_fix_waves) {
+  if (pc.fixlist[0] == 0) {
+    if (blockIdx.x == 0) fix_count(pc, n_fix_waves);
+    return;
+  }
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
   const int gsize = gridDim.x * blockDim.x;
   const int total = hb.tile_prefix[hb.count] * 32;
@@ -422,8 +406,7 @@ hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, i
   int fgrid = 2 * n_cu;
   if (fgrid * (kFixWG / 64) > kMaxProjWaves) fgrid = kMaxProjWaves / (kFixWG / 64);
   hipLaunchKernelGGL(k_fixup, dim3(fgrid), dim3(kFixWG), 0, s, hb, p2);
-  hipLaunchKernelGGL(k_fix_count, dim3(1), dim3(1024), 0, s, p2, fgrid * (kFixWG / 64));
-  hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, p2);
+  hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, p2, fgrid * (kFixWG / 64));
   return hipGetLastError();
 }
 

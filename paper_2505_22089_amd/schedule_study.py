@@ -1,0 +1,107 @@
+"""Host-to-device traffic of pair schedules under a GPU residency cap.
+
+Counts the descriptor bytes each schedule copies host -> HBM for a view
+graph, for three ways of walking the pairs:
+
+* naive: both images of every pair are loaded for that pair and freed
+  after it (no residency at all);
+* sequential: pairs in list order, images kept resident until the cap
+  forces the least recently used one out (a load/free list);
+* MBR: the block schedule of Sec. 2.2 / Algorithm 1 (GPS order, segments of
+  Size_blk images, block rows), computed by the library's scheduler.
+
+Only image sizes and the pair list are needed, so full-size view graphs
+(5,000 images, ~10^5 pairs) are studied without generating descriptors.
+Run: python -m paper_2505_22089_amd.schedule_study
+"""
+from __future__ import annotations
+
+import argparse
+import json
+from collections import OrderedDict
+from typing import Dict, List, Sequence
+
+import numpy as np
+
+from . import chm, synth
+
+
+def naive_bytes(pairs: np.ndarray, desc_bytes: Sequence[int]) -> int:
+    return int(sum(desc_bytes[q] + desc_bytes[d] for q, d in pairs))
+
+
+def sequential_lru(pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Sequence[int],
+                   cap: int) -> Dict[str, int]:
+    """Pairs in order; a missing image is loaded, evicting least recently
+    used images (never the other image of the current pair) until it fits."""
+    res: "OrderedDict[int, None]" = OrderedDict()
+    used = loaded_bytes = loads = peak = 0
+    for q, d in pairs:
+        for i in (int(q), int(d)):
+            if i in res:
+                res.move_to_end(i)
+                continue
+            while used + slot_bytes[i] > cap:
+                victim = next(v for v in res if v not in (int(q), int(d)))
+                used -= slot_bytes[victim]
+                del res[victim]
+            res[i] = None
+            used += slot_bytes[i]
+            loaded_bytes += desc_bytes[i]
+            loads += 1
+            peak = max(peak, used)
+    return {"h2d_bytes": loaded_bytes, "loads": loads, "resident_peak": peak}
+
+
+def mbr(n: int, pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Sequence[int], cap: int,
+        blk: int) -> Dict[str, object]:
+    s = chm.schedule_mbr(n, pairs, slot_bytes, cap, blk)
+    loads = [i for st in s.steps for i in st["load"]]
+    return {"h2d_bytes": int(sum(desc_bytes[i] for i in loads)), "loads": len(loads),
+            "steps": len(s.steps), "iterations": s.iterations, "fallback_pairs": s.fallback_pairs,
+            "dims": s.dims}
+
+
+def grid_graph(rows: int = 50, cols: int = 100, seed: int = 1005) -> np.ndarray:
+    rng = np.random.default_rng(seed)
+    return np.concatenate([synth.band_grid_pairs(rows, cols, 1, 3), synth.cross_links(rng, rows, cols)])
+
+
+def study(name: str, n: int, pairs: np.ndarray, feats: np.ndarray, caps_gb: List[float],
+          blks: List[int]) -> List[dict]:
+    cfg = chm.config()
+    slot = [chm.image_bytes(cfg, int(f)) + 256 for f in feats]
+    desc = [int(f) * 128 for f in feats]
+    floor = int(sum(desc))
+    out = []
+    for cap_gb in caps_gb:
+        cap = int(cap_gb * (1 << 30))
+        row = {"workload": name, "cap_GB": cap_gb, "images": n, "pairs": int(len(pairs)),
+               "floor_bytes": floor, "naive_bytes": naive_bytes(pairs, desc),
+               "sequential": sequential_lru(pairs, slot, desc, cap), "mbr": {}}
+        for blk in blks:
+            row["mbr"][blk] = mbr(n, pairs, slot, desc, cap, blk)
+        out.append(row)
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--caps", default="16,2")
+    ap.add_argument("--blks", default="50,100,200,400,800")
+    a = ap.parse_args()
+    caps = [float(c) for c in a.caps.split(",")]
+    blks = [int(b) for b in a.blks.split(",")]
+    rows = []
+    pairs = grid_graph()
+    rows += study("grid-50x100 x 10000", 5000, pairs, np.full(5000, 10000), caps, blks)
+    strips = synth.offset_grid_pairs(25, 20, synth.STRIP_12)
+    rng = np.random.default_rng(1003)
+    feats = np.round(np.exp(rng.uniform(np.log(2000), np.log(20000), 500))).astype(np.int64)
+    rows += study("strips-25x20 x LU(2k-20k)", 500, strips, feats, [c / 8 for c in caps], blks)
+    for r in rows:
+        print(json.dumps(r))
+
+
+if __name__ == "__main__":
+    main()

@@ -171,7 +171,9 @@ def _expected_overlap(F, centres, feats, pairs, cap_frac):
 
 def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.ndarray,
                    target_overlap: float, cap_frac: float = 0.9, K: int = 8,
-                   measure_pairs: int = 2000) -> Workload:
+                   measure_pairs: int = 2000, progress=None) -> Workload:
+    """Footprint/track model; progress(msg), if given, is called as the
+    (possibly long) generation advances.  Chunked draws equal one draw."""
     rng = np.random.default_rng(seed)
     centres = np.asarray(centres, dtype=np.float64)
     feats = np.asarray(feats, dtype=np.int64)
@@ -194,9 +196,18 @@ def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.n
     pos[:, 1] = rng.uniform(y0, y1, T)
     order = np.argsort(pos[:, 0], kind="stable")
     pos = pos[order]
-    base = sift_like(rng, T)
+    chunk = 1 << 20
+    parts = []
+    for c0 in range(0, T, chunk):
+        parts.append(sift_like(rng, min(chunk, T - c0)))
+        if progress:
+            progress("tracks %d / %d" % (min(T, c0 + chunk), T))
+    base = np.concatenate(parts) if parts else sift_like(rng, 0)
+    del parts
     images, tracks = [], []
     for i, (cx, cy) in enumerate(centres):
+        if progress and i and i % 250 == 0:
+            progress("images %d / %d" % (i, len(centres)))
         a = np.searchsorted(pos[:, 0], cx - F / 2, side="left")
         b = np.searchsorted(pos[:, 0], cx + F / 2, side="right")
         cand = np.arange(a, b)
@@ -282,12 +293,13 @@ def config4(n_images: int = 200, n_feats: int = 40000, k: int = 10, seed: int = 
                           np.full(n_images, n_feats), pairs, 0.30)
 
 
-def config5(rows: int = 50, cols: int = 100, n_feats: int = 10000, seed: int = 1005) -> Workload:
+def config5(rows: int = 50, cols: int = 100, n_feats: int = 10000, seed: int = 1005,
+            progress=None) -> Workload:
     rng = np.random.default_rng(seed)
     pairs = np.concatenate([band_grid_pairs(rows, cols, 1, 3), cross_links(rng, rows, cols)])
     centres = np.array([(c, r) for r in range(rows) for c in range(cols)], dtype=np.float64)
     return track_workload("grid-%dx%d-%d" % (rows, cols, n_feats), seed + 7, centres,
-                          np.full(rows * cols, n_feats), pairs, 0.30)
+                          np.full(rows * cols, n_feats), pairs, 0.30, progress=progress)
 
 
 CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4, 5: config5}

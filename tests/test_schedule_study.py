@@ -1,0 +1,44 @@
+"""Host-only schedule study: traffic counts of the three pair schedules."""
+import numpy as np
+
+from paper_2505_22089_amd import schedule_study as S
+from paper_2505_22089_amd import synth
+
+
+def test_naive_counts_both_images_per_pair():
+    pairs = np.array([[0, 1], [1, 2], [0, 2]], np.int32)
+    assert S.naive_bytes(pairs, [10, 20, 30]) == 30 + 50 + 40
+
+
+def test_sequential_lru_loads_each_image_once_when_everything_fits():
+    pairs = np.array([[0, 1], [1, 2], [2, 0], [0, 1]], np.int32)
+    r = S.sequential_lru(pairs, [1, 1, 1], [5, 6, 7], cap=3)
+    assert r == {"h2d_bytes": 18, "loads": 3, "resident_peak": 3}
+
+
+def test_sequential_lru_evicts_least_recently_used_not_the_partner():
+    # cap of two images: pair (0,2) must evict 1 (least recent other than 0)
+    pairs = np.array([[0, 1], [0, 2], [1, 2]], np.int32)
+    r = S.sequential_lru(pairs, [1, 1, 1], [1, 1, 1], cap=2)
+    # loads: 0, 1, then 2 (evicts 1), then 1 (evicts 0)
+    assert r["loads"] == 4 and r["resident_peak"] == 2
+
+
+def test_mbr_reaches_the_floor_on_a_path_with_room():
+    n = 40
+    pairs = np.array([[i, i + 1] for i in range(n - 1)], np.int32)
+    slot = [100] * n
+    desc = [64] * n
+    r = S.mbr(n, pairs, slot, desc, cap=20 * 100, blk=4)
+    assert r["h2d_bytes"] == n * 64 and r["loads"] == n and r["fallback_pairs"] == 0
+
+
+def test_mbr_never_beats_the_floor_and_never_exceeds_naive_on_a_grid():
+    rng = np.random.default_rng(0)
+    pairs = np.concatenate([synth.band_grid_pairs(6, 12, 1, 3), synth.cross_links(rng, 6, 12)])
+    n = 72
+    slot = [10] * n
+    desc = [8] * n
+    for cap in (200, 120, 60):
+        r = S.mbr(n, pairs, slot, desc, cap=cap, blk=4)
+        assert n * 8 <= r["h2d_bytes"] <= S.naive_bytes(pairs, desc)
