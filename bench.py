@@ -443,16 +443,19 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
+MATCH_SOURCES = ("bucket.hip", "chm_host.cpp", "chm_host.h", "chm_internal.h", "match.hip")
+
+
 def sources_digest():
-    """sha256 over the library's native sources (any change invalidates the
-    recorded counters)."""
+    """sha256 over the sources that shape the match kernel and its data (its
+    code, launch, work list and the bucket tables it reads): any change
+    invalidates the recorded counters."""
     import hashlib
     d = os.path.join(ROOT, "paper_2505_22089_amd", "csrc")
     h = hashlib.sha256()
-    for f in sorted(os.listdir(d)):
-        if f.endswith((".hip", ".cpp", ".h")):
-            h.update(f.encode())
-            h.update(open(os.path.join(d, f), "rb").read())
+    for f in MATCH_SOURCES:
+        h.update(f.encode())
+        h.update(open(os.path.join(d, f), "rb").read())
     return h.hexdigest()
 
 
