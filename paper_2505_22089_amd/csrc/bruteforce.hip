@@ -9,6 +9,13 @@
 // running top-2 of s for the 16 query rows its accumulators hold, over the
 // db columns it sees; lanes are merged with butterflies and splits by a
 // second kernel, which also applies the ratio test.
+//
+// The top-2 runs on packed keys 128 s + (127 - c), c the column inside its
+// 128-column LDS tile: one shift-add forms the key from the accumulator and
+// a per-column bias, a max and a median-of-three keep the two largest, and
+// the tile of the best key is recorded once per tile.  Ties between equal
+// scores cannot change the output (equal best and second distances fail
+// the ratio test for any t_r <= 1), so which column wins one is immaterial.
 #include <climits>
 
 #include "chm_internal.h"
@@ -60,12 +67,12 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
     v ^= 0x80808080u;
     A[ks] = __builtin_bit_cast(i32x4v, v);
   }
-  int32_t s1[16], s2[16], j1[16];
+  int32_t s1[16], s2[16], t1[16];  // best and second keys, tile of the best
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
     s1[e] = INT_MIN;
     s2[e] = INT_MIN;
-    j1[e] = -1;
+    t1[e] = -1;
   }
 
   for (int tile = c0; tile < c1; tile += kBfD) {
@@ -85,9 +92,14 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
         for (int w = 0; w < 4; ++w) nrm = __builtin_amdgcn_sdot4((int)v[w], (int)v[w], nrm, false);
       }
       nrm += __shfl_xor(nrm, 1);
-      if (part == 0) sN[row] = nrm;
+      // key bias of the column: -128 ||y'||^2 + (127 - c); an empty column
+      // (a zero row, dot 0) gets -2^30, below every real key
+      if (part == 0) sN[row] = (g < c1) ? -(nrm << 7) + (127 - row) : -(1 << 30);
     }
     __syncthreads();
+    int32_t before[16];
+#pragma unroll
+    for (int e = 0; e < 16; ++e) before[e] = s1[e];
 #pragma unroll
     for (int blk = 0; blk < kBfD / 32; ++blk) {
       const int crow = blk * 32 + (lane & 31);
@@ -97,25 +109,28 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
         const i32x4v B = *reinterpret_cast<const i32x4v*>(sD + crow * kBfStride + 32 * ks + 16 * half);
         acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[ks], B, acc, 0, 0, 0);
       }
-      const int col = tile + crow;
-      const bool valid = col < c1;
-      const int32_t negn = -sN[crow];
+      const int32_t bias = sN[crow];
 #pragma unroll
       for (int e = 0; e < 16; ++e) {
-        const int32_t s = valid ? (acc[e] << 1) + negn : INT_MIN;
-        s2[e] = med3i(s1[e], s2[e], s);
-        j1[e] = s > s1[e] ? col : j1[e];
-        s1[e] = max(s1[e], s);
+        const int32_t key = (acc[e] << 8) + bias;  // 128 (2 x'.y' - ||y'||^2) + 127 - c
+        s2[e] = med3i(s1[e], s2[e], key);
+        s1[e] = max(s1[e], key);
       }
     }
+#pragma unroll
+    for (int e = 0; e < 16; ++e) t1[e] = s1[e] != before[e] ? tile : t1[e];
   }
-  // merge the 32 lanes that hold the same query rows (lanes of one half)
+  // merge the 32 lanes that hold the same query rows (lanes of one half);
+  // from here on a best key travels with its global column
+  int32_t j1[16];
+#pragma unroll
+  for (int e = 0; e < 16; ++e) j1[e] = s1[e] == INT_MIN ? -1 : t1[e] + (127 - (s1[e] & 127));
 #pragma unroll
   for (int e = 0; e < 16; ++e) {
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
-      const int32_t t1 = __shfl_xor(s1[e], d), u1 = __shfl_xor(j1[e], d), t2 = __shfl_xor(s2[e], d);
-      merge2(s1[e], j1[e], s2[e], t1, u1, t2);
+      const int32_t u = __shfl_xor(s1[e], d), uj = __shfl_xor(j1[e], d), u2 = __shfl_xor(s2[e], d);
+      merge2(s1[e], j1[e], s2[e], u, uj, u2);
     }
     const int row = blockIdx.x * kBfQ + wave * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
     if ((lane & 31) == 0 && row < nq) work[(size_t)blockIdx.y * nq + row] = make_int4(s1[e], j1[e], s2[e], 0);
@@ -143,7 +158,8 @@ __global__ void k_bf_merge(const int4* work, int splits, const uint8_t* Q, int n
     out[i] = -1;
     return;
   }
-  const int64_t e1 = (int64_t)nrm - s1, e2 = (int64_t)nrm - s2;
+  // keys back to scores: s = key >> 7 (arithmetic)
+  const int64_t e1 = (int64_t)nrm - (s1 >> 7), e2 = (int64_t)nrm - (s2 >> 7);
   out[i] = ((int64_t)rb * rb * e1 < (int64_t)ra * ra * e2) ? j1 : -1;
 }
 

@@ -143,25 +143,11 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
       if (p < e) return;
     }
   };
-  // One block of 8 slots: keys, then insertion of those that pass.
-  auto process = [&](const uint4& x0, const uint4& x1) {
-    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-    // Keys of the block, and per slot the wave mask of lanes whose key
-    // could enter the kept list (below the current KT-th key).
-    uint32_t key[8];
-    uint64_t pass[8];
-#pragma unroll
-    for (int k = 0; k < 8; ++k) {
-      const uint4 c = code_at<LDSC>(gcodes, w[k]);
-      const uint32_t h =
-          bcnt_acc(qc.w ^ c.w, bcnt_acc(qc.z ^ c.z, bcnt_acc(qc.y ^ c.y, bcnt_acc(qc.x ^ c.x, 0u))));
-      key[k] = (h << 24) | w[k];
-      pass[k] = __ballot(key[k] < thr);
-    }
-    // Insert the passing keys: each round every lane takes its lowest
-    // remaining passing slot (lanes with none take kNoKey, a no-op), so the
-    // rounds follow the largest per-lane pass count of the wave and the
-    // selection runs on the wave masks.
+  // Insertion of a block's passing keys: each round every lane takes its
+  // lowest remaining passing slot (lanes with none take kNoKey, a no-op), so
+  // the rounds follow the largest per-lane pass count of the wave and the
+  // selection runs on the wave masks.
+  auto drain = [&](const uint32_t (&key)[8], uint64_t (&pass)[8]) {
     uint64_t any = pass[0] | pass[1] | pass[2] | pass[3] | pass[4] | pass[5] | pass[6] | pass[7];
     while (any) {
       uint32_t x = kNoKey;
@@ -179,30 +165,66 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
     }
     thr = top[KT - 1];
   };
-  auto load = [&](uint4& x0, uint4& x1) {
-    x0 = ldg4(mbase + (toff + 4u * (uint32_t)p));
-    x1 = ldg4(mbase + (toff + 4u * (uint32_t)p + 16u));
+  // One block: its 8 code reads are issued first, the previous block's
+  // insertions run while they are in flight, then the block's keys and, per
+  // slot, the wave mask of lanes whose key could enter the kept list (below
+  // the current KT-th key) are formed; they wait for the next step.  A lane
+  // without a block (valid false) reads a harmless one and passes nothing.
+  uint32_t pkey[8];
+  uint64_t ppass[8];
+  auto step = [&](const uint4& x0, const uint4& x1, bool valid) {
+    const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+    uint4 c[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) c[k] = code_at<LDSC>(gcodes, w[k]);
+    drain(pkey, ppass);
+    const uint32_t lim = valid ? thr : 0u;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      const uint32_t h = bcnt_acc(qc.w ^ c[k].w,
+                                  bcnt_acc(qc.z ^ c[k].z, bcnt_acc(qc.y ^ c[k].y, bcnt_acc(qc.x ^ c[k].x, 0u))));
+      pkey[k] = (h << 24) | w[k];
+      ppass[k] = __ballot(pkey[k] < lim);
+    }
+  };
+  // Members of the lane's next block, or of the table's first block (always
+  // present when any lane of the wave has a block) for a lane without one.
+  auto load = [&](uint4& x0, uint4& x1, bool valid) {
+    const uint32_t off = valid ? toff + 4u * (uint32_t)p : 0u;
+    x0 = ldg4(mbase + off);
+    x1 = ldg4(mbase + off + 16u);
   };
   auto advance = [&]() {
     p += 8;
     if (p >= e) next_table();
     return t < a.L;
   };
-  // Two register sets in turn: the next block loads while this one is used.
+  // The wave steps through blocks together (lanes with fewer blocks idle
+  // through the rest); two member register sets alternate, so the next
+  // block's members load while this block is used.
   next_table();
-  if (t < a.L) {
-    uint4 A0, A1, B0, B1;
-    load(A0, A1);
-    for (;;) {
-      const bool more_b = advance();
-      if (more_b) load(B0, B1);
-      process(A0, A1);
-      if (!more_b) break;
-      const bool more_a = advance();
-      if (more_a) load(A0, A1);
-      process(B0, B1);
-      if (!more_a) break;
+  bool cur = t < a.L;
+  if (__ballot(cur) != 0) {
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      pkey[k] = kNoKey;
+      ppass[k] = 0;
     }
+    uint4 A0, A1, B0, B1;
+    load(A0, A1, cur);
+    for (;;) {
+      const bool nb = cur && advance();
+      load(B0, B1, nb);
+      step(A0, A1, cur);
+      cur = nb;
+      if (__ballot(cur) == 0) break;
+      const bool na = cur && advance();
+      load(A0, A1, na);
+      step(B0, B1, cur);
+      cur = na;
+      if (__ballot(cur) == 0) break;
+    }
+    drain(pkey, ppass);
   }
 
   const int64_t o = P.out_off + q;
