@@ -3,7 +3,9 @@
 // members, members ascending inside each bucket).
 //
 // A member is stored as 16 j, the byte offset of db point j's long code, so
-// a matching lane addresses the code with no arithmetic.  Each bucket's range
+// a matching lane addresses the code with no arithmetic.  Images too large
+// for the match kernel's LDS code stage also get their codes copied in
+// bucket order, so that the 8 codes of a block are one contiguous 128 bytes.  Each bucket's range
 // of the members array is padded to a multiple of 8 entries with copies of
 // the bucket's first (smallest) member, and starts at a multiple of 8: a
 // matching lane then reads whole aligned 32-byte blocks of 8 members and
@@ -123,6 +125,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   __syncthreads();
 
   uint32_t* mem = I.members + (size_t)t * I.m_stride;
+  uint4* tc = I.tcodes ? I.tcodes + (size_t)t * I.m_stride : nullptr;  // codes in bucket order
   for (int c = c0; c < c1; ++c) {
     const int i = c * 64 + lane;
     const bool valid = i < n;
@@ -130,7 +133,10 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const uint64_t peers = peers_of(b, valid, hb.m);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t start = valid ? cnt[wave][b] : 0u;
-    if (valid) mem[start + rank] = 16u * (uint32_t)i;
+    if (valid) {
+      mem[start + rank] = 16u * (uint32_t)i;
+      if (tc) tc[start + rank] = I.codes[i];
+    }
     __builtin_amdgcn_wave_barrier();
     if (valid && rank == 0) cnt[wave][b] = start + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
@@ -138,7 +144,10 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   // pads (positions no scattered member takes) and the unused tail
   for (int b = tid; b < nb; b += kBucketWG) {
     const uint32_t c = real[b], pc = (c + 7u) & ~7u;
-    for (uint32_t k = c; k < pc; ++k) mem[pbase[b] + k] = 16u * first[b];
+    for (uint32_t k = c; k < pc; ++k) {
+      mem[pbase[b] + k] = 16u * first[b];
+      if (tc) tc[pbase[b] + k] = I.codes[first[b]];
+    }
   }
   for (int i = (int)s_total + tid; i < I.m_stride; i += kBucketWG) mem[i] = 0;
 }

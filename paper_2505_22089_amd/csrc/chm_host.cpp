@@ -462,13 +462,8 @@ extern "C" chm_status chm_store_set_tuning(chm_store* S, const chm_tuning* t) {
 
 // ------------------------------------------------------------------ plans
 
-static const size_t kLdsBudget = 160 * 1024 - 1024;  // a CU's LDS less a reserve
-
-// Codes the match kernel can stage in LDS: what is left of a CU's LDS after
-// the bucket offsets and the kernel's control words and sort arrays.
 int chm::lds_max_feats(const chm_store* S) {
-  const size_t off = ((size_t)S->cfg.num_tables * (S->nb + 1) + 3) / 4 * 16;
-  return (int)((kLdsBudget - off - kMatchLdsTail) / 16);
+  return lds_code_cap(S->cfg.num_tables, S->cfg.bucket_bits);
 }
 
 static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
@@ -480,6 +475,7 @@ static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
   d.norms = h.norms;
   d.offsets = h.offsets;
   d.members = h.members;
+  d.tcodes = h.tcodes;
   d.n = h.n;
   d.n_pad = h.n_pad;
   d.m_stride = h.m_stride;

@@ -21,6 +21,7 @@ struct ImageDev {
   const int32_t* offsets;   // L x (nb + 1): padded bucket ranges, multiples of 8
   const uint32_t* members;  // L x m_stride code byte offsets (16 j), ascending inside each
                             // bucket, then pads
+  const uint4* tcodes;      // L x m_stride codes in bucket order, or null (small images)
   int32_t n;
   int32_t n_pad;
   int32_t m_stride;         // members per table: n + 7 * min(nb, n), rounded up to 8
@@ -43,11 +44,6 @@ struct WorkItem {
 // has its own L2): bin b holds items[bin_begin[b] .. bin_begin[b+1]).
 constexpr int kMaxBins = 16;
 
-// Items of at most kSortMax queries are processed in order of walk length.
-// LDS after the staged codes and offsets: two control words (16 B), the
-// sort's histogram (256 u32), order (u16) and lengths (u8).
-constexpr int kSortMax = 2048;
-constexpr size_t kMatchLdsTail = 16 + 256 * 4 + kSortMax * 3;
 
 struct MatchArgs {
   const PairDev* pairs;
@@ -67,15 +63,31 @@ struct MatchArgs {
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
 };
 
+// Items of at most kSortMax queries are processed in order of walk length.
+// LDS after the staged codes and offsets: two control words (16 B), the
+// sort's histogram (256 u32), order (u16) and lengths (u8).
+constexpr int kSortMax = 2048;
+constexpr size_t kMatchLdsTail = 16 + 256 * 4 + kSortMax * 3;
+constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // a CU's LDS less a reserve
+
+// Codes the match kernel can stage in LDS for a db image: what is left of
+// the LDS after the bucket offsets and the kernel's control words and sort.
+__host__ __device__ constexpr int lds_code_cap(int L, int m) {
+  return (int)((kLdsBudget - ((size_t)L * ((1u << m) + 1) + 3) / 4 * 16 - kMatchLdsTail) / 16);
+}
+
 // Sections of one image slot in the arena (byte offsets from the slot
 // start, each 256-byte aligned): descriptors n x 128, long codes n x 16,
 // bucket ids L x n_pad, squared norms n x 4, offsets L x (2^m + 1) int32,
-// members L x m_stride u32.  Used by the host to size and address slots and
+// members L x m_stride u32, and for images too large for the LDS code stage
+// the codes again in bucket order, L x m_stride x 16 (tcodes[t][pos] is the
+// code of members[t][pos]).  Used by the host to size and address slots and
 // by the hashing kernels to address a slot from its base alone.
 struct ImageLayout {
-  uint64_t desc, codes, ids, norms, offsets, members, total;
+  uint64_t desc, codes, ids, norms, offsets, members, tcodes, total;
   int n_pad;
   int m_stride;
+  bool has_tcodes;
 };
 
 __host__ __device__ inline uint64_t layout_round(uint64_t v, uint64_t a) { return (v + a - 1) / a * a; }
@@ -94,6 +106,8 @@ __host__ __device__ inline ImageLayout image_layout(int L, int m, int n) {
   l.norms = o;   o += layout_round((uint64_t)n * 4, 256);
   l.offsets = o; o += layout_round((uint64_t)L * (nb + 1) * 4, 256);
   l.members = o; o += layout_round((uint64_t)L * l.m_stride * 4, 256);
+  l.has_tcodes = n > lds_code_cap(L, m);
+  l.tcodes = o;  o += l.has_tcodes ? layout_round((uint64_t)L * l.m_stride * 16, 256) : 0;
   l.total = o;
   return l;
 }
@@ -116,6 +130,7 @@ struct HashImage {
   uint32_t* norms;
   int32_t* offsets;
   uint32_t* members;        // 16 * db index (the byte offset of its code)
+  uint4* tcodes;            // codes in bucket order, or null
   int32_t n;
   int32_t n_pad;
   int32_t m_stride;
@@ -138,6 +153,7 @@ __host__ __device__ inline HashImage hash_image(const HashSlot& s, int L, int m)
   h.norms = reinterpret_cast<uint32_t*>(s.base + l.norms);
   h.offsets = reinterpret_cast<int32_t*>(s.base + l.offsets);
   h.members = reinterpret_cast<uint32_t*>(s.base + l.members);
+  h.tcodes = l.has_tcodes ? reinterpret_cast<uint4*>(s.base + l.tcodes) : nullptr;
   h.n = s.n;
   h.n_pad = l.n_pad;
   h.m_stride = l.m_stride;

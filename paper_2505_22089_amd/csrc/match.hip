@@ -127,6 +127,7 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   // like (h, j).
   const char* mbase = uniform_ptr(P.d.members);
   const char* gcodes = uniform_ptr(P.d.codes);
+  const char* tcodes = P.d.tcodes ? uniform_ptr(P.d.tcodes) : nullptr;
   const uint32_t mstride = 4u * (uint32_t)P.d.m_stride;
   const int stride = a.nb + 1;
   // Walk the L buckets as one sequence of aligned 8-member blocks; toff and
@@ -172,11 +173,16 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   // without a block (valid false) reads a harmless one and passes nothing.
   uint32_t pkey[8];
   uint64_t ppass[8];
-  auto step = [&](const uint4& x0, const uint4& x1, bool valid) {
+  auto step = [&](const uint4& x0, const uint4& x1, uint32_t moff, bool valid) {
     const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
     uint4 c[8];
+    if (!LDSC && tcodes) {  // the block's codes, contiguous at 4x its members' offset
 #pragma unroll
-    for (int k = 0; k < 8; ++k) c[k] = code_at<LDSC>(gcodes, w[k]);
+      for (int k = 0; k < 8; ++k) c[k] = ldg4(tcodes + 4u * moff + 16u * k);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 8; ++k) c[k] = code_at<LDSC>(gcodes, w[k]);
+    }
     drain(pkey, ppass);
     const uint32_t lim = valid ? thr : 0u;
 #pragma unroll
@@ -189,8 +195,8 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   };
   // Members of the lane's next block, or of the table's first block (always
   // present when any lane of the wave has a block) for a lane without one.
-  auto load = [&](uint4& x0, uint4& x1, bool valid) {
-    const uint32_t off = valid ? toff + 4u * (uint32_t)p : 0u;
+  auto load = [&](uint4& x0, uint4& x1, uint32_t& off, bool valid) {
+    off = valid ? toff + 4u * (uint32_t)p : 0u;
     x0 = ldg4(mbase + off);
     x1 = ldg4(mbase + off + 16u);
   };
@@ -211,16 +217,17 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
       ppass[k] = 0;
     }
     uint4 A0, A1, B0, B1;
-    load(A0, A1, cur);
+    uint32_t offA, offB;
+    load(A0, A1, offA, cur);
     for (;;) {
       const bool nb = cur && advance();
-      load(B0, B1, nb);
-      step(A0, A1, cur);
+      load(B0, B1, offB, nb);
+      step(A0, A1, offA, cur);
       cur = nb;
       if (__ballot(cur) == 0) break;
       const bool na = cur && advance();
-      load(A0, A1, na);
-      step(B0, B1, cur);
+      load(A0, A1, offA, na);
+      step(B0, B1, offB, cur);
       cur = na;
       if (__ballot(cur) == 0) break;
     }
