@@ -1,0 +1,88 @@
+"""Match quality of cascade hashing against the planted correspondences.
+
+For the 50-image workload (tracks planted by the footprint model), runs the
+batched GPU matcher for a grid of K (candidates kept, Sec. 2.3.1 step (3))
+and ratio thresholds t_r (step (4)), with and without a mutual check
+(i -> j kept only if j -> i is also returned by the reverse pair), and
+scores precision and recall against the ground truth: a match i -> j is
+correct when descriptor i of the query and j of the db image observe the
+same track.  Recall counts the query descriptors whose track the db image
+observes.  Run on a GPU: python -m paper_2505_22089_amd.quality_study
+"""
+from __future__ import annotations
+
+import argparse
+import json
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+from . import chm, synth
+
+
+def _score(wl, pairs: np.ndarray, offs: np.ndarray, out: np.ndarray,
+           keep: List[np.ndarray] = None) -> Dict[str, float]:
+    tp = fp = possible = 0
+    for p, (q, d) in enumerate(pairs):
+        m = out[offs[p]:offs[p + 1]]
+        if keep is not None:
+            m = np.where(keep[p], m, -1)
+        tq, td = wl.tracks[q], wl.tracks[d]
+        present = np.isin(tq, td[td >= 0]) & (tq >= 0)
+        possible += int(present.sum())
+        hit = m >= 0
+        ok = hit & (tq >= 0)
+        ok[ok] = tq[ok] == td[m[ok]]
+        tp += int(ok.sum())
+        fp += int(hit.sum() - ok.sum())
+    return {"matches": tp + fp, "precision": tp / max(1, tp + fp), "recall": tp / max(1, possible)}
+
+
+def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, m: int = 8) -> List[dict]:
+    import torch
+    wl = synth.config2()
+    pairs = wl.pairs
+    index = {(int(q), int(d)): p for p, (q, d) in enumerate(pairs)}
+    rev = np.array([index.get((int(d), int(q)), -1) for q, d in pairs])
+    dev = torch.device("cuda:0")
+    descs = [torch.from_numpy(x).to(dev) for x in wl.images]
+    rows = []
+    for K in Ks:
+        for ra in ratios:
+            cfg = chm.config(L=L, m=m, K=K, ratio=ra)
+            need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256
+                                                       for x in wl.images)
+            arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device=dev)
+            st = chm.Store(cfg, wl.W[:128 + L * m], wl.mu, arena)
+            st.load(list(range(len(wl.images))), descs)
+            offs = chm.out_offsets(st, pairs)
+            out_t = torch.empty(int(offs[-1]), dtype=torch.int32, device=dev)
+            chm.match_pairs(st, pairs, out_t, chm.MATCH_BATCHED, offs=offs)
+            out = out_t.cpu().numpy()
+            st.close()
+            # mutual check on the pairs whose reverse pair is listed
+            keep = []
+            for p, (q, d) in enumerate(pairs):
+                mq = out[offs[p]:offs[p + 1]]
+                r = rev[p]
+                if r < 0:
+                    keep.append(np.ones(len(mq), bool))
+                    continue
+                md = out[offs[r]:offs[r + 1]]
+                ok = mq >= 0
+                ok[ok] = md[mq[ok]] == np.nonzero(ok)[0]
+                keep.append(ok)
+            row = {"K": K, "ratio": "%d/%d" % ra, "plain": _score(wl, pairs, offs, out),
+                   "mutual": _score(wl, pairs, offs, out, keep)}
+            rows.append(row)
+            print(json.dumps(row), flush=True)
+    return rows
+
+
+def main():
+    argparse.ArgumentParser().parse_args()
+    run()
+
+
+if __name__ == "__main__":
+    main()

@@ -42,3 +42,20 @@ def test_mbr_never_beats_the_floor_and_never_exceeds_naive_on_a_grid():
     for cap in (200, 120, 60):
         r = S.mbr(n, pairs, slot, desc, cap=cap, blk=4)
         assert n * 8 <= r["h2d_bytes"] <= S.naive_bytes(pairs, desc)
+
+
+def test_quality_scoring_counts_planted_tracks():
+    from paper_2505_22089_amd import quality_study as Q
+
+    class W:
+        tracks = [np.array([5, 6, -1, 7]), np.array([6, 9, 5])]
+    pairs = np.array([[0, 1]], np.int32)
+    offs = np.array([0, 4], np.int64)
+    # query 0 (track 5) -> db 2 (track 5): right; query 1 (track 6) -> db 1 (track 9): wrong;
+    # query 2 (no track) -> db 0: wrong; query 3 (track 7, absent from db) -> none
+    out = np.array([2, 1, 0, -1], np.int32)
+    r = Q._score(W, pairs, offs, out)
+    assert r == {"matches": 3, "precision": 1 / 3, "recall": 1 / 2}
+    keep = [np.array([True, False, False, True])]
+    r = Q._score(W, pairs, offs, out, keep)
+    assert r == {"matches": 1, "precision": 1.0, "recall": 1 / 2}
