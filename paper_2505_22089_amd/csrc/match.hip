@@ -2,10 +2,12 @@
 //
 // One lane owns one query descriptor x_i of the query image:
 //  (1) for each table t it walks the db image's bucket beta_t(x_i); the
-//      bucket's members (ascending db indices, u16) are read as aligned
-//      16-byte blocks of eight, one block ahead of use;
+//      bucket's members (16 j for db index j, ascending, padded to whole
+//      blocks) are read as aligned 32-byte blocks of eight, one block ahead
+//      of use, and the codes of a block are read before the previous
+//      block's insertions run;
 //  (2) for each candidate j it forms h = popcount(c(x_i) xor c(y_j)) over the
-//      128-bit long codes and the key (h << 24) | j, whose order is the
+//      128-bit long codes and the key (h << 24) | 16 j, whose order is the
 //      paper's ranking by Hamming distance with ties broken by db index;
 //  (3) it keeps the KT smallest distinct keys in registers: a sorted list
 //      updated with median-of-three steps; a key equal to a kept one is a
@@ -20,13 +22,15 @@
 //      accumulation, and applies the ratio test on squared distances
 //      (den^2 * d1 < num^2 * d2).
 //
-// Work items are (pair, query range).  Batched plans run one persistent grid
-// that dequeues items with atomic counters, one bin of items per XCD (the
-// items of a db image share a bin, so its data stays in that XCD's L2);
-// inside a work-group, wavefronts take 64-query chunks of the item
-// dynamically.  Plain plans launch one grid
-// per pair.  With LDSC the db image's codes and bucket offsets are staged in
-// LDS once per item (skipped when consecutive items share the db image).
+// Work items are (pair, query range); an item's queries are taken in order
+// of walk length, so the lanes of a wavefront walk about as far.  Batched
+// plans run one persistent grid that dequeues items with atomic counters,
+// one bin of items per XCD (the items of a db image share a bin, so its
+// data stays in that XCD's L2); inside a work-group, wavefronts take
+// 64-query chunks of the item dynamically.  Plain plans launch one grid per
+// pair.  With LDSC the db image's codes and bucket offsets are staged in LDS
+// once per item (skipped when consecutive items share the db image); larger
+// db images are read from their bucket-ordered code copy.
 #include "chm_internal.h"
 
 namespace chm {
