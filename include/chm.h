@@ -224,7 +224,9 @@ typedef struct chm_tuning {
   int32_t queries_per_item; /* queries per batched work item, multiple of 64, 64..8192 */
   int32_t wg_threads;       /* 256 or 1024 */
   int32_t lds_codes;        /* 1: stage the db image's codes in LDS when they fit */
-  int32_t grid_per_cu;      /* persistent work-groups per compute unit, 1..8 */
+  int32_t grid_per_cu;      /* persistent work-groups per compute unit when no db
+                               image of a batched plan is staged in LDS, 1..8 (a
+                               launch that stages runs one per compute unit) */
 } chm_tuning;
 
 chm_status chm_store_get_tuning(const chm_store *store, chm_tuning *out);

@@ -25,8 +25,9 @@ CANDIDATES: List[Dict[str, int]] = [
     dict(queries_per_item=4096, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=512, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=1024, wg_threads=256, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=1024, wg_threads=1024, lds_codes=0, grid_per_cu=2),
+    dict(queries_per_item=1024, wg_threads=256, lds_codes=0, grid_per_cu=2),
     dict(queries_per_item=256, wg_threads=256, lds_codes=0, grid_per_cu=4),
-    dict(queries_per_item=1024, wg_threads=256, lds_codes=0, grid_per_cu=8),
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chm_autotune.json")

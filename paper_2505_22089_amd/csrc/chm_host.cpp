@@ -215,10 +215,10 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   S->dFix = (unsigned long long*)(S->base + kHdrFix);
   S->dFixList = (uint32_t*)(S->base + kHdrFixList);
   std::memset(&S->stats, 0, sizeof S->stats);
-  S->tuning.queries_per_item = 1024;
+  S->tuning.queries_per_item = 2048;
   S->tuning.wg_threads = 1024;
   S->tuning.lds_codes = 1;
-  S->tuning.grid_per_cu = 4;
+  S->tuning.grid_per_cu = 1;
   hipError_t e = hipMemcpy(S->dW, W.data(), W.size() * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dTau, tau.data(), tau.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dCmu, cmu.data(), cmu.size() * 8, hipMemcpyHostToDevice);
@@ -530,61 +530,60 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
       pl->pair_lds[p] = lds;
     }
   } else {
-    // Items of a class are dealt into one bin per XCD, whole db images at a
-    // time (longest total first onto the least loaded bin), so the work-groups
-    // of an XCD share the db images' codes, members and descriptors in their
-    // L2; inside a bin, a db image's items are consecutive, longest first.
+    // All items go to one persistent launch: the LDS-staging kernel when any
+    // db image fits the code stage (it reads larger ones from HBM in the same
+    // launch), else the HBM-only kernel.  Items are dealt into one bin per
+    // XCD, whole db images at a time (largest total first onto the least
+    // loaded bin), so the work-groups of an XCD share the db images' codes,
+    // members and descriptors in their L2; inside a bin, a db image's items
+    // are consecutive, longest first.
     const int qpi = pl->tun.queries_per_item;
     const int nbins = std::max(1, S->n_xcd);
-    for (int cls = 0; cls < 2; ++cls) {
-      std::map<const void*, std::vector<std::pair<double, WorkItem>>> groups;
-      for (int p = 0; p < P; ++p) {
-        const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
-        if (lds != (cls == 0)) continue;
-        for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
-          WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
-          const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
-          groups[pd[p].d.codes].push_back({cost, w});
-        }
+    std::map<const void*, std::vector<std::pair<double, WorkItem>>> groups;
+    for (int p = 0; p < P; ++p) {
+      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+      pl->lds_launch |= lds;
+      for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
+        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
+        const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
+        groups[pd[p].d.codes].push_back({cost, w});
       }
-      std::vector<std::pair<double, std::vector<std::pair<double, WorkItem>>*>> order;
-      for (auto& g : groups) {
-        double c = 0;
-        for (auto& x : g.second) c += x.first;
-        std::sort(g.second.begin(), g.second.end(),
-                  [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
-                    if (x.first != y.first) return x.first > y.first;
-                    if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
-                    return x.second.q0 < y.second.q0;
-                  });
-        order.push_back({c, &g.second});
-      }
-      std::stable_sort(order.begin(), order.end(),
-                       [](const auto& x, const auto& y) { return x.first > y.first; });
-      std::vector<std::vector<WorkItem>> bins(nbins);
-      std::vector<double> load(nbins, 0.0);
-      for (auto& g : order) {
-        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-        load[b] += g.first;
-        for (auto& x : *g.second) bins[b].push_back(x.second);
-      }
-      int32_t* bb = pl->bins[cls];
-      bb[0] = (int32_t)items.size();
-      for (int b = 0; b < nbins; ++b) {
-        items.insert(items.end(), bins[b].begin(), bins[b].end());
-        bb[b + 1] = (int32_t)items.size();
-      }
-      pl->n_bins = nbins;
-      if (cls == 0) pl->n_lds_items = (int)items.size();
     }
+    std::vector<std::pair<double, std::vector<std::pair<double, WorkItem>>*>> order;
+    for (auto& g : groups) {
+      double c = 0;
+      for (auto& x : g.second) c += x.first;
+      std::sort(g.second.begin(), g.second.end(),
+                [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
+                  if (x.first != y.first) return x.first > y.first;
+                  if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
+                  return x.second.q0 < y.second.q0;
+                });
+      order.push_back({c, &g.second});
+    }
+    std::stable_sort(order.begin(), order.end(),
+                     [](const auto& x, const auto& y) { return x.first > y.first; });
+    std::vector<std::vector<WorkItem>> bins(nbins);
+    std::vector<double> load(nbins, 0.0);
+    for (auto& g : order) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[b] += g.first;
+      for (auto& x : *g.second) bins[b].push_back(x.second);
+    }
+    pl->bins[0] = 0;
+    for (int b = 0; b < nbins; ++b) {
+      items.insert(items.end(), bins[b].begin(), bins[b].end());
+      pl->bins[b + 1] = (int32_t)items.size();
+    }
+    pl->n_bins = nbins;
   }
   pl->n_items = (int)items.size();
 
   const uint64_t pairs_bytes = round_up(sizeof(PairDev) * (size_t)std::max(P, 1), 256);
   const uint64_t items_bytes = round_up(sizeof(WorkItem) * (size_t)std::max(pl->n_items, 1), 256);
-  const uint64_t queue_bytes = 256;  // 2 x kMaxBins counters
-  const uint64_t bins_bytes = 256;   // 2 x (kMaxBins + 1) offsets, relative to the class
-  static_assert(2 * kMaxBins * 4 <= 256 && 2 * (kMaxBins + 1) * 4 <= 256, "plan tail");
+  const uint64_t queue_bytes = 256;  // kMaxBins counters
+  const uint64_t bins_bytes = 256;   // kMaxBins + 1 item offsets
+  static_assert(kMaxBins * 4 <= 256 && (kMaxBins + 1) * 4 <= 256, "plan tail");
   pl->mem_bytes = pairs_bytes + items_bytes + queue_bytes + bins_bytes;
   if (!S->arena.alloc(pl->mem_bytes, &pl->mem_off)) {
     delete pl;
@@ -595,15 +594,13 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   pl->dItems = (WorkItem*)(S->base + pl->mem_off + pairs_bytes);
   pl->dQueue = (uint32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes);
   pl->dBins = (int32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes + queue_bytes);
-  int32_t hbins[2][kMaxBins + 1] = {};
-  for (int cls = 0; cls < 2; ++cls)
-    for (int b = 0; b <= pl->n_bins; ++b) hbins[cls][b] = pl->bins[cls][b] - pl->bins[cls][0];
+  const int32_t* hbins = pl->bins;
   hipStream_t s = (hipStream_t)stream;
   hipError_t e = hipSuccess;
   if (P) e = hipMemcpyAsync(pl->dPairs, pd.data(), sizeof(PairDev) * P, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && pl->n_items)
     e = hipMemcpyAsync(pl->dItems, items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, hbins, sizeof hbins, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, hbins, sizeof pl->bins, hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);
   if (e != hipSuccess) {
     S->arena.release(pl->mem_off, pl->mem_bytes);
@@ -631,28 +628,16 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {
     hipStream_t cs = S->cap_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, 2 * kMaxBins, cs);
-    const int nl = pl->n_lds_items, ng = pl->n_items - pl->n_lds_items;
-    if (e == hipSuccess && nl > 0) {
+    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, kMaxBins, cs);
+    if (e == hipSuccess) {
       MatchArgs x = a;
-      x.items = pl->dItems;
-      x.n_items = nl;
-      x.queue = pl->dQueue;
-      x.bin_begin = pl->dBins;
+      x.n_items = pl->n_items;
       x.n_bins = pl->n_bins;
-      const int grid = std::min(nl, S->n_cu);  // the LDS stage allows one work-group per CU
-      e = launch_match(x, a.K, pl->tun.wg_threads, true, true, grid, cs);
-    }
-    if (e == hipSuccess && ng > 0) {
-      MatchArgs x = a;
-      x.items = pl->dItems + nl;
-      x.n_items = ng;
-      x.queue = pl->dQueue + kMaxBins;
-      x.bin_begin = pl->dBins + (kMaxBins + 1);
-      x.n_bins = pl->n_bins;
-      x.lds_max_feats = 0;
-      const int grid = std::min(ng, S->n_cu * pl->tun.grid_per_cu);
-      e = launch_match(x, a.K, 256, false, true, grid, cs);
+      // the LDS stage allows one work-group per CU
+      const int per_cu = pl->lds_launch ? 1 : pl->tun.grid_per_cu;
+      if (!pl->lds_launch) x.lds_max_feats = 0;
+      const int grid = std::min(pl->n_items, S->n_cu * per_cu);
+      e = launch_match(x, a.K, pl->tun.wg_threads, pl->lds_launch, true, grid, cs);
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);

@@ -62,9 +62,9 @@ struct chm_plan {
   int mode = 0;
   int n_pairs = 0;
   int n_items = 0;
-  int n_lds_items = 0;
   int n_bins = 1;
-  int32_t bins[2][chm::kMaxBins + 1] = {};  // item offsets of the bins (absolute)
+  bool lds_launch = false;                 // batched: the launch stages codes in LDS
+  int32_t bins[chm::kMaxBins + 1] = {};    // item offsets of the bins
   int lds_max = 0;
   int32_t* out = nullptr;
   uint32_t* topk = nullptr;
@@ -72,8 +72,8 @@ struct chm_plan {
   uint64_t mem_off = 0, mem_bytes = 0;
   chm::PairDev* dPairs = nullptr;
   chm::WorkItem* dItems = nullptr;
-  uint32_t* dQueue = nullptr;  // 2 x kMaxBins counters (LDS class, global class)
-  int32_t* dBins = nullptr;    // 2 x (kMaxBins + 1) bin offsets
+  uint32_t* dQueue = nullptr;  // kMaxBins dequeue counters, one per bin
+  int32_t* dBins = nullptr;    // kMaxBins + 1 bin offsets
   std::vector<int> pair_begin, pair_count;
   std::vector<char> pair_lds;
   chm::MatchArgs args;

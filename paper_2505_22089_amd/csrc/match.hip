@@ -109,8 +109,24 @@ __device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t t, uint32
   return r;
 }
 
+// Sum over the 8 lanes of each aligned group of 8 (quad swaps, then the
+// mirror inside the half-row, which pairs each quad with the other one).
+__device__ __forceinline__ uint32_t sum8(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  return v;
+}
+
+__device__ __forceinline__ uint32_t lane_read(uint32_t v, int src_lane) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src_lane << 2, (int)v);
+}
+
+// Called by all 64 lanes of the wavefront (the re-rank is cooperative);
+// a lane with valid false owns no query (q is any valid index) and writes
+// nothing.
 template <int KT, bool LDSC>
-__device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P, int q,
+__device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P, int q, bool valid,
                                             const int32_t* offs) {
   const uint4 qc = ldg4(P.q.codes + q);
   uint32_t qb0 = 0, qb1 = 0;  // bucket ids of the query, one byte per table
@@ -212,7 +228,8 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   // The wave steps through blocks together (lanes with fewer blocks idle
   // through the rest); two member register sets alternate, so the next
   // block's members load while this block is used.
-  next_table();
+  if (valid) next_table();
+  else t = a.L;
   bool cur = t < a.L;
   if (__ballot(cur) != 0) {
 #pragma unroll
@@ -239,49 +256,73 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   }
 
   const int64_t o = P.out_off + q;
-  if (a.topk) {  // keys as (h << 24) | j
+  if (a.topk && valid) {  // keys as (h << 24) | j
 #pragma unroll
     for (int k = 0; k < KT; ++k)
       if (k < a.K)
         a.topk[o * a.K + k] = top[k] == kNoKey ? kNoKey : (top[k] & 0xFF000000u) | ((top[k] & 0xFFFFFFu) >> 4);
   }
 
-  // Euclidean re-rank of the first K candidates and ratio test.
-  const uint4* xq = reinterpret_cast<const uint4*>(P.q.desc + (size_t)q * kDim);
-  uint4 x[8];
-#pragma unroll
-  for (int v = 0; v < 8; ++v) x[v] = ldg4(xq + v);
-  const uint32_t nq = *(gcu32*)(P.q.norms + q);
+  // Exact re-rank of the first K candidates and ratio test, with the
+  // wavefront's lanes in groups of 8: in round g, group r serves the query
+  // of lane 8 g + r, each of its lanes reading one 16-byte segment of the
+  // query and of candidate k, so a load instruction reads 8 whole
+  // descriptors.  The group's partial dot products are summed across its
+  // lanes, and the squared distance goes back to the query's own lane,
+  // which keeps the two smallest in candidate order.
+  const int lane = __lane_id();
+  const int seg = lane & 7;
+  const uint32_t xoff = 16u * (uint32_t)seg;
   uint32_t d1 = 0xFFFFFFFFu, d2 = 0xFFFFFFFFu;
   int j1 = -1, cnt = 0;
+#pragma unroll 1
+  for (int g = 0; g < 8; ++g) {
+    const int src = 8 * g + (lane >> 3);
+    const int qs = (int)lane_read((uint32_t)q, src);
+    const bool vs = lane_read(valid ? 1u : 0u, src) != 0u;
+    const uint8_t* xp = P.q.desc + (size_t)qs * kDim + xoff;
+    const uint4 xs = ldg4(xp);
+    const uint32_t nqs = *(gcu32*)(P.q.norms + qs);
+    const bool mine = (lane >> 3) == g;
 #pragma unroll
-  for (int k = 0; k < KT; ++k) {
-    if (k < a.K && top[k] != kNoKey) {
-      const uint32_t j = (top[k] & 0xFFFFFFu) >> 4;
-      const uint4* yp = reinterpret_cast<const uint4*>(P.d.desc + (size_t)j * kDim);
-      uint32_t dot = 0;
+    for (int k0 = 0; k0 < KT; k0 += 8) {
+      constexpr int KB = KT < 8 ? KT : 8;
+      uint4 y[KB];
+      uint32_t ny[KB];
 #pragma unroll
-      for (int v = 0; v < 8; ++v) {
-        const uint4 y = ldg4(yp + v);
-        dot = __builtin_amdgcn_udot4(x[v].x, y.x, dot, false);
-        dot = __builtin_amdgcn_udot4(x[v].y, y.y, dot, false);
-        dot = __builtin_amdgcn_udot4(x[v].z, y.z, dot, false);
-        dot = __builtin_amdgcn_udot4(x[v].w, y.w, dot, false);
+      for (int kk = 0; kk < KB; ++kk) {  // loads of the candidates first
+        const uint32_t key = lane_read(top[k0 + kk], src);
+        const bool ok = vs && k0 + kk < a.K && key != kNoKey;
+        const uint32_t j = (key & 0xFFFFFFu) >> 4;
+        // a lane without a candidate re-reads the query's own segment
+        y[kk] = ldg4(ok ? P.d.desc + (size_t)j * kDim + xoff : xp);
+        ny[kk] = *(gcu32*)(ok ? P.d.norms + j : P.q.norms + qs);
       }
-      const uint32_t e2 = nq + *(gcu32*)(P.d.norms + j) - 2u * dot;
-      if (e2 < d1) {
-        d2 = d1;
-        d1 = e2;
-        j1 = (int)j;
-      } else if (e2 < d2) {
-        d2 = e2;
+#pragma unroll
+      for (int kk = 0; kk < KB; ++kk) {
+        const int k = k0 + kk;
+        uint32_t dot = __builtin_amdgcn_udot4(xs.x, y[kk].x, 0u, false);
+        dot = __builtin_amdgcn_udot4(xs.y, y[kk].y, dot, false);
+        dot = __builtin_amdgcn_udot4(xs.z, y[kk].z, dot, false);
+        dot = __builtin_amdgcn_udot4(xs.w, y[kk].w, dot, false);
+        dot = sum8(dot);
+        const uint32_t e2 = lane_read(nqs + ny[kk] - 2u * dot, 8 * seg);
+        if (mine && valid && k < a.K && top[k] != kNoKey) {
+          if (e2 < d1) {
+            d2 = d1;
+            d1 = e2;
+            j1 = (int)((top[k] & 0xFFFFFFu) >> 4);
+          } else if (e2 < d2) {
+            d2 = e2;
+          }
+          ++cnt;
+        }
       }
-      ++cnt;
     }
   }
   const bool pass = cnt >= 2 && (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
                                     (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2;
-  a.out[o] = pass ? j1 : -1;
+  if (valid) a.out[o] = pass ? j1 : -1;
 }
 
 // LDS of the per-item query sort: order (u16), walk length (u8), histogram.
@@ -352,7 +393,9 @@ __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, c
     c = __builtin_amdgcn_readfirstlane(__shfl(c, 0));  // uniform across the wave
     if (w.q0 + c >= w.q1) break;
     const int i = c + lane;
-    if (w.q0 + i < w.q1) match_query<KT, LDSC>(a, P, w.q0 + (sorted ? (int)s.order[i] : i), offs);
+    const bool valid = w.q0 + i < w.q1;
+    const int qi = valid ? (sorted ? (int)s.order[i] : i) : 0;
+    match_query<KT, LDSC>(a, P, w.q0 + qi, valid, offs);
   }
 }
 
