@@ -290,6 +290,46 @@ chm_status chm_run_schedule(chm_store *store, const chm_schedule *s, const int32
                             const int32_t *h_n_feats, const int64_t *h_out_offsets,
                             int32_t *d_out, void *stream);
 
+/* SAO local geometric constraint (Sec. 2.3.3, Fig. 4): outlier removal of
+ * initial matches on host threads (the paper runs it on the CPU beside the
+ * GPU matching).  Host memory only; no GPU call.
+ *
+ * For every directed pair p (query image h_pairs[2p], db image h_pairs[2p+1])
+ * the initial matches are h_match[h_offs[p] .. h_offs[p+1]), one per query
+ * row (db row or -1), the layout the matcher writes.  Each match i -> m(i)
+ * of a pair with M matches is scored as follows.
+ *   - N = min(n_neighbors, M - 1).
+ *   - O_p holds the N other matches whose query keypoints are nearest to
+ *     query keypoint i, by squared distance, ties by the smaller query row.
+ *   - O_q likewise holds the N other matches whose db keypoints are nearest
+ *     to db keypoint m(i); a db keypoint matched by several queries is one
+ *     point per match.
+ *   - Both lists are put in angular order around their centre:
+ *     counter-clockwise from +x, angles in [0, 2 pi), a neighbour on the
+ *     centre first, equal angles by distance then row.
+ *   - CED is the cyclic edit distance between the two lists of query rows:
+ *     the least Levenshtein distance (unit costs) over their rotations.
+ *   - The match is kept when the dissimilarity CED / N is at most
+ *     score_num / score_den, that is CED * score_den <= score_num * N
+ *     (N = 0 keeps it, with CED 0).
+ *
+ *   h_kp[img]   : h_n_feats[img] x 2 int32 keypoint coordinates (x, y) of
+ *                 image img, any unit, |x|, |y| < 2^30 (all comparisons are
+ *                 exact integer arithmetic).
+ *   n_images    : entries of h_kp and h_n_feats.
+ *   h_offs      : n_pairs + 1 non-decreasing offsets; pair p's range has the
+ *                 query image's row count.
+ *   n_neighbors : 1..32 (the paper's figure uses 6).
+ *   n_threads   : worker threads; <= 0 uses every hardware thread.
+ *   h_out       : filtered matches (the match or -1); may be h_match itself.
+ *   h_ced       : optional (NULL), CED per query row, -1 where unmatched.
+ * Errors: CHM_E_INVALID_ARG for a NULL array, an image id or db row out of
+ * range, a coordinate out of range, or bad offsets or parameters. */
+chm_status chm_sao_filter(int32_t n_pairs, const int32_t *h_pairs, const int32_t *const *h_kp,
+                          const int32_t *h_n_feats, int32_t n_images, const int64_t *h_offs,
+                          const int32_t *h_match, int32_t n_neighbors, int32_t score_num,
+                          int32_t score_den, int32_t n_threads, int32_t *h_out, int32_t *h_ced);
+
 #ifdef __cplusplus
 }
 #endif

@@ -60,7 +60,7 @@ EXPORTS = [
     "chm_match_pairs", "chm_store_get_tuning", "chm_store_set_tuning",
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
-    "chm_run_schedule",
+    "chm_run_schedule", "chm_sao_filter",
 ]
 
 _lib = None
@@ -103,6 +103,7 @@ def lib():
             "chm_schedule_free": (None, [vp]),
             "chm_gps_order": (i32, [i32, vp, i32, vp, i32, vp]),
             "chm_run_schedule": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
+            "chm_sao_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -390,3 +391,25 @@ def run_schedule(store: Store, sched: Schedule, pairs: np.ndarray, descs: Sequen
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     _check(lib().chm_run_schedule(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
                                   _np_ptr(ns), _np_ptr(offs), _dev_ptr(out), _stream(stream)))
+
+
+def sao_filter(keypoints: Sequence[np.ndarray], pairs: np.ndarray, offs: np.ndarray,
+               matches: np.ndarray, n_neighbors: int = 6, threshold=(1, 2), n_threads: int = 0,
+               want_ced: bool = False):
+    """SAO local constraint (Sec. 2.3.3) on host threads: filtered matches
+    (and the CED per query row when want_ced).  keypoints[img] is an (n, 2)
+    int32 array; matches is the matcher's output for `pairs` laid out by
+    `offs`."""
+    kps = [np.ascontiguousarray(k, dtype=np.int32) for k in keypoints]
+    nf = np.array([k.shape[0] for k in kps], dtype=np.int32)
+    ptrs = (C.c_void_p * max(1, len(kps)))(*[k.ctypes.data for k in kps])
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    matches = np.ascontiguousarray(matches, dtype=np.int32)
+    out = np.empty_like(matches)
+    ced = np.empty_like(matches) if want_ced else None
+    _check(lib().chm_sao_filter(len(pairs), _np_ptr(pairs), C.cast(ptrs, C.c_void_p), _np_ptr(nf),
+                                len(kps), _np_ptr(offs), _np_ptr(matches), n_neighbors,
+                                int(threshold[0]), int(threshold[1]), n_threads, _np_ptr(out),
+                                _np_ptr(ced)))
+    return (out, ced) if want_ced else out

@@ -7,7 +7,11 @@ and ratio thresholds t_r (step (4)), with and without a mutual check
 scores precision and recall against the ground truth: a match i -> j is
 correct when descriptor i of the query and j of the db image observe the
 same track.  Recall counts the query descriptors whose track the db image
-observes.  Run on a GPU: python -m paper_2505_22089_amd.quality_study
+observes.  With --repeat-frac the workload has repeated texture (that
+fraction of the tracks look like other tracks elsewhere), which makes false
+matches that pass the ratio test; each row then also scores the matches kept
+by the SAO local constraint (Sec. 2.3.3) at a few dissimilarity thresholds.
+Run on a GPU: python -m paper_2505_22089_amd.quality_study [--repeat-frac 0.3]
 """
 from __future__ import annotations
 
@@ -38,9 +42,11 @@ def _score(wl, pairs: np.ndarray, offs: np.ndarray, out: np.ndarray,
     return {"matches": tp + fp, "precision": tp / max(1, tp + fp), "recall": tp / max(1, possible)}
 
 
-def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, m: int = 8) -> List[dict]:
+def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, m: int = 8,
+        repeat_frac: float = 0.0, sao_thresholds=((1, 3), (1, 2), (2, 3))) -> List[dict]:
     import torch
-    wl = synth.config2()
+    wl = synth.config2(repeat_frac=repeat_frac)
+    kps = synth.keypoints(wl)
     pairs = wl.pairs
     index = {(int(q), int(d)): p for p, (q, d) in enumerate(pairs)}
     rev = np.array([index.get((int(d), int(q)), -1) for q, d in pairs])
@@ -72,16 +78,21 @@ def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, 
                 ok = mq >= 0
                 ok[ok] = md[mq[ok]] == np.nonzero(ok)[0]
                 keep.append(ok)
-            row = {"K": K, "ratio": "%d/%d" % ra, "plain": _score(wl, pairs, offs, out),
-                   "mutual": _score(wl, pairs, offs, out, keep)}
+            row = {"K": K, "ratio": "%d/%d" % ra, "repeat_frac": repeat_frac,
+                   "plain": _score(wl, pairs, offs, out), "mutual": _score(wl, pairs, offs, out, keep)}
+            for th in sao_thresholds:
+                f = chm.sao_filter(kps, pairs, offs, out, 6, th)
+                row["sao %d/%d" % th] = _score(wl, pairs, offs, f)
             rows.append(row)
             print(json.dumps(row), flush=True)
     return rows
 
 
 def main():
-    argparse.ArgumentParser().parse_args()
-    run()
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--repeat-frac", type=float, default=0.0)
+    a = ap.parse_args()
+    run(repeat_frac=a.repeat_frac)
 
 
 if __name__ == "__main__":

@@ -15,8 +15,8 @@ Recipe
 ------
 * SIFT-like descriptor: z = |N(0, 40^2)|^128 in float64, x = clip(rint(512 z /
   ||z||_2), 0, 255) as uint8 (rint is round-half-even).
-* Noisy copy of x: clip(rint(x + 8 * N(0, 1)), 0, 255), the normal draws in
-  float32, not renormalised.
+* Noisy copy of x: clip(rint(x + sigma * N(0, 1)), 0, 255), sigma = 8 unless
+  stated, the normal draws in float32, not renormalised.
 * Multi-image workloads use a footprint/track model: image centres in the
   plane, square footprints of side F, a global set of tracks (position + base
   descriptor) with uniform density; an image observes the tracks inside its
@@ -98,6 +98,7 @@ class Workload:
     tracks: Optional[List[np.ndarray]] = None   # per image, track id per row (-1 fresh)
     gt: Optional[np.ndarray] = None             # (G, 2) planted (row in A, row in B), pair 0
     centres: Optional[np.ndarray] = None
+    track_pos: Optional[np.ndarray] = None      # (T, 2) plane position of each track
     meta: Dict = field(default_factory=dict)
 
     @property
@@ -171,9 +172,13 @@ def _expected_overlap(F, centres, feats, pairs, cap_frac):
 
 def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.ndarray,
                    target_overlap: float, cap_frac: float = 0.9, K: int = 8,
-                   measure_pairs: int = 2000, progress=None) -> Workload:
+                   measure_pairs: int = 2000, progress=None, noise: float = 8.0,
+                   repeat_frac: float = 0.0, repeat_sigma: float = 4.0) -> Workload:
     """Footprint/track model; progress(msg), if given, is called as the
-    (possibly long) generation advances.  Chunked draws equal one draw."""
+    (possibly long) generation advances.  Chunked draws equal one draw.
+    repeat_frac > 0 models repeated texture: that fraction of the tracks
+    take a noisy copy (repeat_sigma) of another track's base descriptor, so
+    look-alike points sit at unrelated places."""
     rng = np.random.default_rng(seed)
     centres = np.asarray(centres, dtype=np.float64)
     feats = np.asarray(feats, dtype=np.int64)
@@ -204,6 +209,11 @@ def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.n
             progress("tracks %d / %d" % (min(T, c0 + chunk), T))
     base = np.concatenate(parts) if parts else sift_like(rng, 0)
     del parts
+    if repeat_frac > 0 and T > 1:
+        nrep = int(repeat_frac * T)
+        dst = rng.choice(T, size=nrep, replace=False)
+        src = rng.integers(0, T, size=nrep)
+        base[dst] = noisy_copy(rng, base[src], repeat_sigma)
     images, tracks = [], []
     for i, (cx, cy) in enumerate(centres):
         if progress and i and i % 250 == 0:
@@ -216,7 +226,7 @@ def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.n
         cap = int(cap_frac * n_i)
         if len(cand) > cap:
             cand = np.sort(rng.choice(cand, size=cap, replace=False))
-        obs = noisy_copy(rng, base[cand])
+        obs = noisy_copy(rng, base[cand], noise)
         fresh = sift_like(rng, n_i - len(cand))
         x = np.concatenate([obs, fresh], axis=0)
         tid = np.concatenate([cand.astype(np.int64), -np.ones(n_i - len(cand), np.int64)])
@@ -239,7 +249,33 @@ def track_workload(name: str, seed: int, centres: np.ndarray, feats, pairs: np.n
                 overlap_mean=float(ov.mean()), overlap_min=float(ov.min()),
                 overlap_max=float(ov.max()), overlap_sampled_pairs=int(len(samp)))
     return Workload(name=name, images=images, pairs=pairs, W=W, mu=mu, K=K,
-                    tracks=tracks, centres=centres, meta=meta)
+                    tracks=tracks, centres=centres, track_pos=pos, meta=meta)
+
+
+def keypoints(wl: Workload, size_px: float = 4000.0, sigma_px: float = 1.0, subpix: int = 16,
+              seed: int = 77) -> List[np.ndarray]:
+    """Integer keypoint coordinates (units of 1/subpix pixel), one (n, 2)
+    int32 array per image of a footprint/track workload.
+
+    Image i sees its square footprint (side F, centre c_i) as size_px pixels,
+    turned by a heading drawn uniformly in [0, 2 pi): a tracked row sits at
+    R(heading) (p_track - c_i) size_px / F + size_px / 2 plus N(0, sigma_px^2)
+    per axis; a fresh row is uniform over [0, size_px)^2.  The draws use
+    their own generator, so the descriptors are unchanged."""
+    if wl.tracks is None or wl.track_pos is None:
+        raise ValueError("keypoints need a footprint/track workload")
+    rng = np.random.default_rng(seed)
+    F = float(wl.meta["footprint"])
+    out = []
+    for i, tid in enumerate(wl.tracks):
+        th = rng.uniform(0.0, 2.0 * np.pi)
+        rot = np.array([[np.cos(th), -np.sin(th)], [np.sin(th), np.cos(th)]])
+        xy = rng.uniform(0.0, size_px, size=(len(tid), 2))
+        t = tid >= 0
+        rel = (wl.track_pos[tid[t]] - wl.centres[i]) * (size_px / F)
+        xy[t] = rel @ rot.T + size_px / 2 + rng.normal(0.0, sigma_px, size=(int(t.sum()), 2))
+        out.append(np.rint(xy * subpix).astype(np.int32))
+    return out
 
 
 # ---------------------------------------------------------------- the five workloads
@@ -262,14 +298,15 @@ def config1(n: int = 2000, planted: int = 1000, seed: int = 1001) -> Workload:
 
 
 def config2(n_images: int = 50, n_feats: int = 8000, k: int = 8, K: int = 8,
-            seed: int = 1002) -> Workload:
+            seed: int = 1002, noise: float = 8.0, repeat_frac: float = 0.0) -> Workload:
     """n_images x n_feats, centres uniform in a square, k-NN directed pairs, 40% overlap."""
     rng = np.random.default_rng(seed)
     side = np.sqrt(n_images)
     centres = rng.uniform(0, side, size=(n_images, 2))
     pairs = knn_pairs(centres, k)
     return track_workload("knn-%dx%d" % (n_images, n_feats), seed + 7, centres,
-                          np.full(n_images, n_feats), pairs, 0.40, K=K)
+                          np.full(n_images, n_feats), pairs, 0.40, K=K, noise=noise,
+                          repeat_frac=repeat_frac)
 
 
 def config3(strips: int = 25, per_strip: int = 20, lo: int = 2000, hi: int = 20000,
