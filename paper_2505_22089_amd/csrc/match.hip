@@ -35,6 +35,12 @@
 
 namespace chm {
 
+// Lanes that share one candidate descriptor in the re-rank (4 or 8).
+#ifndef CHM_RERANK_LANES
+#define CHM_RERANK_LANES 4
+#endif
+constexpr int kRerankLanes = CHM_RERANK_LANES;
+
 typedef uint32_t v4u __attribute__((ext_vector_type(4)));
 typedef __attribute__((address_space(1))) const v4u gcv4u;
 typedef __attribute__((address_space(1))) const uint32_t gcu32;
@@ -109,12 +115,15 @@ __device__ __forceinline__ uint32_t sel_lanes(uint64_t lanes, uint32_t t, uint32
   return r;
 }
 
-// Sum over the 8 lanes of each aligned group of 8 (quad swaps, then the
-// mirror inside the half-row, which pairs each quad with the other one).
-__device__ __forceinline__ uint32_t sum8(uint32_t v) {
+// Sum over the G lanes of each aligned group of G (G = 4 or 8): quad
+// swaps, then for G = 8 the mirror inside the half-row, which pairs each
+// quad with the other one.
+template <int G>
+__device__ __forceinline__ uint32_t sum_lanes(uint32_t v) {
+  static_assert(G == 4 || G == 8, "groups of 4 or 8 lanes");
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0xB1, 0xF, 0xF, false);   // quad_perm 1,0,3,2
   v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x4E, 0xF, 0xF, false);   // quad_perm 2,3,0,1
-  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
+  if (G == 8) v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x141, 0xF, 0xF, false);  // row_half_mirror
   return v;
 }
 
@@ -264,65 +273,76 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   }
 
   // Exact re-rank of the first K candidates and ratio test, with the
-  // wavefront's lanes in groups of 8: in round g, group r serves the query
-  // of lane 8 g + r, each of its lanes reading one 16-byte segment of the
-  // query and of candidate k, so a load instruction reads 8 whole
-  // descriptors.  The group's partial dot products are summed across its
-  // lanes, and the squared distance goes back to the query's own lane,
-  // which keeps the two smallest in candidate order.
+  // wavefront's lanes in groups of kRerankLanes: in round g, group r serves
+  // the query of lane (64 / kRerankLanes) g + r, each of its lanes reading
+  // one 128 / kRerankLanes-byte slice of the query and of candidate k, so a
+  // load instruction covers whole descriptors.  The group sums its partial
+  // dot products across its lanes, keeps the two smallest distances in
+  // candidate order, applies the ratio test and hands the verdict to the
+  // query's own lane.
+  constexpr int G = kRerankLanes;
+  constexpr int NG = 64 / G;             // groups (queries served per round)
+  constexpr int SL = kDim / G / 16;      // 16-byte loads per lane per descriptor
   const int lane = __lane_id();
-  const int seg = lane & 7;
-  const uint32_t xoff = 16u * (uint32_t)seg;
-  uint32_t d1 = 0xFFFFFFFFu, d2 = 0xFFFFFFFFu;
-  int j1 = -1, cnt = 0;
+  const uint32_t xoff = (uint32_t)(lane % G) * (kDim / G);
+  const char* qdesc = uniform_ptr(P.q.desc);
+  const char* ddesc = uniform_ptr(P.d.desc);
+  const char* qnorm = uniform_ptr(P.q.norms);
+  const char* dnorm = uniform_ptr(P.d.norms);
+  int result = -1;
+  if (P.d.n > 0) {  // else no query has a candidate (and row 0 does not exist)
 #pragma unroll 1
-  for (int g = 0; g < 8; ++g) {
-    const int src = 8 * g + (lane >> 3);
-    const int qs = (int)lane_read((uint32_t)q, src);
-    const bool vs = lane_read(valid ? 1u : 0u, src) != 0u;
-    const uint8_t* xp = P.q.desc + (size_t)qs * kDim + xoff;
-    const uint4 xs = ldg4(xp);
-    const uint32_t nqs = *(gcu32*)(P.q.norms + qs);
-    const bool mine = (lane >> 3) == g;
+    for (int g = 0; g < G; ++g) {
+      const int src = NG * g + lane / G;
+      const uint32_t qs = lane_read((uint32_t)q, src);
+      const bool vs = lane_read(valid ? 1u : 0u, src) != 0u;
+      uint4 xs[SL];
 #pragma unroll
-    for (int k0 = 0; k0 < KT; k0 += 8) {
-      constexpr int KB = KT < 8 ? KT : 8;
-      uint4 y[KB];
-      uint32_t ny[KB];
+      for (int v = 0; v < SL; ++v) xs[v] = ldg4(qdesc + (qs * (uint32_t)kDim + xoff + 16u * v));
+      const uint32_t nqs = *(gcu32*)(qnorm + 4u * qs);
+      uint32_t d1 = 0xFFFFFFFFu, d2 = 0xFFFFFFFFu, j1 = 0xFFFFFFFFu, cnt = 0;
+      // candidates in chunks of KB (loads of a chunk, then its arithmetic)
+      constexpr int KB = KT < 8 / SL ? KT : 8 / SL;
 #pragma unroll
-      for (int kk = 0; kk < KB; ++kk) {  // loads of the candidates first
-        const uint32_t key = lane_read(top[k0 + kk], src);
-        const bool ok = vs && k0 + kk < a.K && key != kNoKey;
-        const uint32_t j = (key & 0xFFFFFFu) >> 4;
-        // a lane without a candidate re-reads the query's own segment
-        y[kk] = ldg4(ok ? P.d.desc + (size_t)j * kDim + xoff : xp);
-        ny[kk] = *(gcu32*)(ok ? P.d.norms + j : P.q.norms + qs);
-      }
+      for (int k0 = 0; k0 < KT; k0 += KB) {
+        uint4 y[KB][SL];
+        uint32_t ny[KB], jj[KB];
+        bool ok[KB];
 #pragma unroll
-      for (int kk = 0; kk < KB; ++kk) {
-        const int k = k0 + kk;
-        uint32_t dot = __builtin_amdgcn_udot4(xs.x, y[kk].x, 0u, false);
-        dot = __builtin_amdgcn_udot4(xs.y, y[kk].y, dot, false);
-        dot = __builtin_amdgcn_udot4(xs.z, y[kk].z, dot, false);
-        dot = __builtin_amdgcn_udot4(xs.w, y[kk].w, dot, false);
-        dot = sum8(dot);
-        const uint32_t e2 = lane_read(nqs + ny[kk] - 2u * dot, 8 * seg);
-        if (mine && valid && k < a.K && top[k] != kNoKey) {
-          if (e2 < d1) {
-            d2 = d1;
-            d1 = e2;
-            j1 = (int)((top[k] & 0xFFFFFFu) >> 4);
-          } else if (e2 < d2) {
-            d2 = e2;
+        for (int kk = 0; kk < KB; ++kk) {  // loads of the candidates first
+          const uint32_t key = lane_read(top[k0 + kk], src);
+          ok[kk] = vs && k0 + kk < a.K && key != kNoKey;
+          jj[kk] = (key & 0xFFFFFFu) >> 4;
+          const uint32_t j = ok[kk] ? jj[kk] : 0u;  // a lane without a candidate reads row 0
+#pragma unroll
+          for (int v = 0; v < SL; ++v) y[kk][v] = ldg4(ddesc + (j * (uint32_t)kDim + xoff + 16u * v));
+          ny[kk] = *(gcu32*)(dnorm + 4u * j);
+        }
+#pragma unroll
+        for (int kk = 0; kk < KB; ++kk) {
+          uint32_t dot = 0;
+#pragma unroll
+          for (int v = 0; v < SL; ++v) {
+            dot = __builtin_amdgcn_udot4(xs[v].x, y[kk][v].x, dot, false);
+            dot = __builtin_amdgcn_udot4(xs[v].y, y[kk][v].y, dot, false);
+            dot = __builtin_amdgcn_udot4(xs[v].z, y[kk][v].z, dot, false);
+            dot = __builtin_amdgcn_udot4(xs[v].w, y[kk][v].w, dot, false);
           }
-          ++cnt;
+          dot = sum_lanes<G>(dot);
+          const uint32_t e2 = ok[kk] ? nqs + ny[kk] - 2u * dot : 0xFFFFFFFFu;
+          j1 = e2 < d1 ? jj[kk] : j1;     // first strictly smallest in candidate order
+          d2 = med3u(d1, e2, d2);         // second smallest of {d1, d2, e2} (d1 <= d2)
+          d1 = min(d1, e2);
+          cnt += ok[kk] ? 1u : 0u;
         }
       }
+      const bool pass = cnt >= 2 && (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
+                                        (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2;
+      const uint32_t got = lane_read(pass ? j1 : 0xFFFFFFFFu, (lane % NG) * G);
+      if (lane / NG == g) result = (int)got;
     }
   }
-  const bool pass = cnt >= 2 && (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
-                                    (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2;
-  if (valid) a.out[o] = pass ? j1 : -1;
+  if (valid) a.out[o] = result;
 }
 
 // LDS of the per-item query sort: order (u16), walk length (u8), histogram.
