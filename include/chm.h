@@ -63,7 +63,7 @@ typedef struct chm_config {
   int32_t ratio_num;      /* t_r = ratio_num / ratio_den, 0 < num <= den <= 46340 */
   int32_t ratio_den;
   int32_t proj_precision; /* CHM_PROJ_BF16 or CHM_PROJ_FP32 (MFMA input type) */
-  int32_t reserved;       /* must be 0 */
+  int32_t flags;          /* CHM_ACCEPT_SINGLE or 0 */
   double fixup_rel;       /* a projection p_r(x) = W_r.x - c_r (c_r = W_r.mu) is
                              recomputed in fp64 when its fp32 value v has
                              |v| < fixup_rel * (||W_r||_2 * ||x||_2 + |c_r|);
@@ -74,6 +74,12 @@ typedef struct chm_config {
                              value in the range keeps every bit exact; 1e-4
                              (the default) recomputes the fewest */
 } chm_config;
+
+/* Flag of chm_config.flags.  The ratio test needs a second candidate; by
+ * default a query with a single candidate gets no match.  With this flag its
+ * second distance counts as infinite and the single candidate is accepted
+ * (the other reading of Sec. 2.3.1 step (4)). */
+#define CHM_ACCEPT_SINGLE 1
 
 /* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-4). */
 void chm_config_default(chm_config *cfg);

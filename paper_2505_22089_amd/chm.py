@@ -19,6 +19,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchm.so")
 
 ABI_VERSION = 1
+ACCEPT_SINGLE = 1
 PROJ_BF16, PROJ_FP32 = 0, 1
 MATCH_PLAIN, MATCH_BATCHED = 0, 1
 MAX_FEATS = 65535
@@ -36,7 +37,7 @@ class ChmError(RuntimeError):
 class Config(C.Structure):
     _fields_ = [("abi_version", C.c_uint32), ("num_tables", C.c_int32), ("bucket_bits", C.c_int32),
                 ("top_k", C.c_int32), ("ratio_num", C.c_int32), ("ratio_den", C.c_int32),
-                ("proj_precision", C.c_int32), ("reserved", C.c_int32), ("fixup_rel", C.c_double)]
+                ("proj_precision", C.c_int32), ("flags", C.c_int32), ("fixup_rel", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -141,13 +142,15 @@ def _stream(stream) -> Optional[int]:
     return stream.cuda_stream if hasattr(stream, "cuda_stream") else int(stream)
 
 
-def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-4) -> Config:
+def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-4,
+           accept_single=False) -> Config:
     c = Config()
     lib().chm_config_default(C.byref(c))
     c.num_tables, c.bucket_bits, c.top_k = L, m, K
     c.ratio_num, c.ratio_den = ratio
     c.proj_precision = precision
     c.fixup_rel = fixup_rel
+    c.flags = ACCEPT_SINGLE if accept_single else 0
     return c
 
 

@@ -60,6 +60,7 @@ struct MatchArgs {
   int32_t K;
   int32_t ratio_num;
   int32_t ratio_den;
+  int32_t accept_single;  // a single candidate passes the ratio test
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
 };
 

@@ -336,8 +336,10 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
           cnt += ok[kk] ? 1u : 0u;
         }
       }
-      const bool pass = cnt >= 2 && (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
-                                        (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2;
+      // d2 is infinite with one candidate: it passes only under accept_single
+      const bool pass = cnt >= 2 ? (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
+                                       (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2
+                                 : cnt == 1 && a.accept_single != 0;
       const uint32_t got = lane_read(pass ? j1 : 0xFFFFFFFFu, (lane % NG) * G);
       if (lane / NG == g) result = (int)got;
     }

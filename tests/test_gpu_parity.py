@@ -115,7 +115,8 @@ def check_matches(st, wl, pairs, mode, K):
                 H[i] = O.hash_image(wl.images[i], wl.W[:128 + st.cfg.num_tables * st.cfg.bucket_bits],
                                     wl.mu, st.cfg.num_tables, st.cfg.bucket_bits)
         ro, rt, _ = O.match_pair(H[q], H[d], st.cfg.num_tables, st.cfg.bucket_bits, K,
-                                 wl.ratio, want_topk=True)
+                                 wl.ratio, want_topk=True,
+                                 accept_single=bool(st.cfg.flags & chm.ACCEPT_SINGLE))
         a, b = offs[p], offs[p + 1]
         assert np.array_equal(topk[a:b], rt), "top-K keys of pair %d (%d -> %d)" % (p, q, d)
         assert np.array_equal(out[a:b], ro), "matches of pair %d (%d -> %d)" % (p, q, d)
@@ -130,6 +131,18 @@ def test_match_parity_config1(mode):
     out = check_matches(st, wl, [(0, 1), (1, 0), (0, 0)], mode, 2)
     gt = {int(a): int(b) for a, b in wl.gt}
     assert np.mean([out[a] == b for a, b in gt.items()]) > 0.9
+
+
+@pytest.mark.parametrize("mode", [chm.MATCH_PLAIN, chm.MATCH_BATCHED])
+def test_match_parity_accept_single(mode):
+    """The d2 = infinity reading: a query with exactly one candidate takes it.
+    Small db images and two tables make one-candidate queries common."""
+    wl = small_workload([600, 40, 25, 1], seed=31)
+    st = new_store(wl, L=2, accept_single=True)
+    load_all(st, wl.images)
+    out = check_matches(st, wl, [(0, 1), (0, 2), (0, 3), (1, 0)], mode, wl.K)
+    assert (out >= 0).any()
+    st.close()
 
 
 @pytest.mark.parametrize("mode", [chm.MATCH_PLAIN, chm.MATCH_BATCHED])

@@ -29,6 +29,30 @@ def bf16_exact(bits: int) -> Fraction:
     return -v if s else v
 
 
+def test_accept_single_takes_the_lone_candidate(orc):
+    """Step (4) needs a second candidate; under the other reading (d2 infinite)
+    a query with exactly one candidate takes it and nothing else changes.
+    A one-point db image with one table and no bucket bits gives every query
+    exactly one candidate."""
+    rng = np.random.default_rng(8)
+    W = synth.projection_weights(rows=128)
+    A, B = synth.sift_like(rng, 50), synth.sift_like(rng, 1)
+    mu = synth.centring_vector([A, B])
+    hq, hd = orc.hash_image(A, W, mu, 1, 0), orc.hash_image(B, W, mu, 1, 0)
+    assert (orc.match_pair(hq, hd, 1, 0, 8)[0] == -1).all()
+    assert (orc.match_pair(hq, hd, 1, 0, 8, accept_single=True)[0] == 0).all()
+    # on a real workload the flag changes exactly the one-candidate queries
+    wl = synth.config2(n_images=3, n_feats=400, k=1)
+    Wl = wl.W[:128 + 2 * 8]
+    H = [orc.hash_image(x, Wl, wl.mu, 2, 8) for x in wl.images]
+    a, topk, _ = orc.match_pair(H[0], H[1], 2, 8, 8, want_topk=True)
+    b, _, _ = orc.match_pair(H[0], H[1], 2, 8, 8, accept_single=True)
+    one = (topk[:, 0] != 0xFFFFFFFF) & (topk[:, 1] == 0xFFFFFFFF)
+    assert one.sum() > 10
+    assert np.array_equal(b[one], (topk[one, 0] & 0xFFFFFF).astype(np.int32))
+    assert np.array_equal(b[~one], a[~one])
+
+
 def code_int(words) -> int:
     return sum(int(w) << (32 * k) for k, w in enumerate(words))
 
