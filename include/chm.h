@@ -336,6 +336,29 @@ chm_status chm_sao_filter(int32_t n_pairs, const int32_t *h_pairs, const int32_t
                           const int32_t *h_match, int32_t n_neighbors, int32_t score_num,
                           int32_t score_den, int32_t n_threads, int32_t *h_out, int32_t *h_ced);
 
+/* SAO on the device: the scores and verdicts of chm_sao_filter for
+ * n_neighbors 1..8, one work-group per pair (Sec. 2.3.3, Fig. 4).
+ *   d_kp        : host array of n_images device pointers; d_kp[img] holds
+ *                 h_n_feats[img] x 2 int32 keypoints, |x|, |y| < 2^30.
+ *   h_pairs, h_n_feats, h_offs : as in chm_sao_filter (host memory).
+ *   d_match     : device matches laid out by h_offs (the matcher's output).
+ *   d_out       : device filtered matches; d_ced (optional) device CED per
+ *                 query row (-1 where unmatched).  Neither may be d_match.
+ *   d_work      : 256-byte aligned device scratch of chm_sao_work_bytes
+ *                 (n_pairs, largest query image) bytes (CHM_E_CAPACITY if
+ *                 smaller).  When the work completes, its first int32
+ *                 holds the number of pairs whose input broke the contract
+ *                 (a db row outside the db image, a coordinate out of
+ *                 range); such pairs keep no match.
+ * The call uploads the pair list (synchronising `stream` once) and then
+ * enqueues the kernel on `stream`. */
+chm_status chm_sao_work_bytes(int32_t n_pairs, int32_t max_query_rows, uint64_t *out_bytes);
+chm_status chm_sao_filter_device(int32_t n_pairs, const int32_t *h_pairs, const int32_t *const *d_kp,
+                                 const int32_t *h_n_feats, int32_t n_images, const int64_t *h_offs,
+                                 const int32_t *d_match, int32_t n_neighbors, int32_t score_num,
+                                 int32_t score_den, int32_t *d_out, int32_t *d_ced, void *d_work,
+                                 uint64_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

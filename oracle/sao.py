@@ -94,16 +94,20 @@ def angular_order(centre: Tuple[int, int], pts: Sequence[Tuple[int, int]],
 def nearest(centre: Tuple[int, int], pts: np.ndarray, labels: np.ndarray, own: int,
             n: int) -> List[int]:
     """Indices (into pts) of the n nearest points other than label `own`,
-    by squared distance, ties by label."""
-    d2 = [(int(pts[k, 0]) - int(centre[0])) ** 2 + (int(pts[k, 1]) - int(centre[1])) ** 2
-          for k in range(len(pts))]
-    order = sorted((d2[k], int(labels[k]), k) for k in range(len(pts)) if int(labels[k]) != own)
-    return [k for _, _, k in order[:n]]
+    by squared distance, ties by label (int64: exact below 2^30)."""
+    pts = np.asarray(pts, dtype=np.int64)
+    labels = np.asarray(labels, dtype=np.int64)
+    d2 = (pts[:, 0] - int(centre[0])) ** 2 + (pts[:, 1] - int(centre[1])) ** 2
+    keep = np.nonzero(labels != own)[0]
+    order = keep[np.lexsort((labels[keep], d2[keep]))]
+    return [int(k) for k in order[:n]]
 
 
 def sao_pair(kp_q: np.ndarray, kp_d: np.ndarray, match: np.ndarray, n_neighbors: int = 6,
-             threshold: Tuple[int, int] = (1, 2)) -> Tuple[np.ndarray, np.ndarray]:
-    """(CED per query row, -1 where unmatched; filtered matches)."""
+             threshold: Tuple[int, int] = (1, 2),
+             only_rows: Optional[Sequence[int]] = None) -> Tuple[np.ndarray, np.ndarray]:
+    """(CED per query row, -1 where unmatched; filtered matches).  With
+    only_rows, just those query rows are scored (the others stay -1)."""
     match = np.asarray(match)
     rows = np.nonzero(match >= 0)[0]
     M = len(rows)
@@ -113,7 +117,10 @@ def sao_pair(kp_q: np.ndarray, kp_d: np.ndarray, match: np.ndarray, n_neighbors:
     ced = np.full(len(match), -1, np.int64)
     out = np.full(len(match), -1, np.int32)
     num, den = threshold
+    wanted = None if only_rows is None else set(int(r) for r in only_rows)
     for a, i in enumerate(rows):
+        if wanted is not None and int(i) not in wanted:
+            continue
         if N == 0:
             ced[i] = 0
         else:

@@ -61,7 +61,7 @@ EXPORTS = [
     "chm_match_pairs", "chm_store_get_tuning", "chm_store_set_tuning",
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
-    "chm_run_schedule", "chm_sao_filter",
+    "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
 ]
 
 _lib = None
@@ -105,6 +105,8 @@ def lib():
             "chm_gps_order": (i32, [i32, vp, i32, vp, i32, vp]),
             "chm_run_schedule": (i32, [vp, vp, vp, i32, vp, vp, vp, vp, vp]),
             "chm_sao_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, i32, vp, vp]),
+            "chm_sao_work_bytes": (i32, [i32, i32, P(u64)]),
+            "chm_sao_filter_device": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, u64, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -416,3 +418,39 @@ def sao_filter(keypoints: Sequence[np.ndarray], pairs: np.ndarray, offs: np.ndar
                                 int(threshold[0]), int(threshold[1]), n_threads, _np_ptr(out),
                                 _np_ptr(ced)))
     return (out, ced) if want_ced else out
+
+
+def sao_work_bytes(n_pairs: int, max_query_rows: int) -> int:
+    v = C.c_uint64()
+    _check(lib().chm_sao_work_bytes(int(n_pairs), int(max_query_rows), C.byref(v)))
+    return int(v.value)
+
+
+def sao_filter_device(keypoints, pairs: np.ndarray, offs: np.ndarray, match, out, ced=None, work=None,
+                      n_neighbors: int = 6, threshold=(1, 2), stream=None):
+    """SAO on the device (n_neighbors <= 8): `keypoints[img]` is a device
+    (n, 2) int32 tensor, `match`/`out`/`ced` device int32 tensors laid out
+    by `offs`, `work` a device uint8 tensor of sao_work_bytes() bytes
+    (allocated here when None).  Returns the work tensor; its first int32 is
+    the number of pairs whose input broke the contract (see
+    sao_input_errors)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nf = np.array([0 if k is None else int(k.shape[0]) for k in keypoints], dtype=np.int32)
+    ptrs = (C.c_void_p * max(1, len(keypoints)))(*[0 if k is None else _dev_ptr(k) for k in keypoints])
+    if work is None:
+        import torch
+        nmax = int(max((nf[q] for q in pairs[:, 0]), default=1))
+        work = torch.empty(sao_work_bytes(len(pairs), nmax) + 256, dtype=torch.uint8, device=match.device)
+        work = work[(-work.data_ptr()) % 256:]
+    _check(lib().chm_sao_filter_device(len(pairs), _np_ptr(pairs), C.cast(ptrs, C.c_void_p), _np_ptr(nf),
+                                       len(keypoints), _np_ptr(offs), _dev_ptr(match), n_neighbors,
+                                       int(threshold[0]), int(threshold[1]), _dev_ptr(out), _dev_ptr(ced),
+                                       _dev_ptr(work), int(work.numel()), _stream(stream)))
+    return work
+
+
+def sao_input_errors(work) -> int:
+    """Pairs of the last device SAO call on `work` whose input broke the
+    contract (waits for the call)."""
+    return int(work[:4].view(dtype=__import__("torch").int32).item())

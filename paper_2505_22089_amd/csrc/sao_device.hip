@@ -1,0 +1,536 @@
+// SAO local geometric constraint (Sec. 2.3.3, Fig. 4) on the device: the same
+// scores as the host implementation, for up to 8 neighbours.
+//
+// One work-group per pair (grid-stride over the pairs), each with its own
+// scratch slab in the caller's work buffer:
+//  1. the pair's matched query rows are compacted in row order (a block scan
+//     of the match flags), so a compact index orders like the query row that
+//     labels the match;
+//  2. for the query image and then the db image, the matched keypoints are
+//     counting-sorted into a uniform grid (about two points per cell), and
+//     every match finds its N nearest other matches by an exact ring search
+//     over the cells (64-bit squared distances, ties by compact index),
+//     stopping once the next ring's distance bound reaches the N-th distance;
+//  3. each match sorts its two neighbour lists by angle (half-plane, then
+//     the sign of a 64-bit cross product) and takes the cyclic edit distance
+//     of the two label sequences as the least Levenshtein distance over the
+//     rotations of one of them (Maes, 1990).
+// All geometry is exact for coordinates below 2^30 in magnitude.  A pair
+// whose input breaks the contract (a db row outside the db image, or a
+// coordinate out of range) keeps no match and is counted in the first word
+// of the work buffer; every index stays inside its buffer whatever the input.
+#include <algorithm>
+#include <vector>
+
+#include "chm.h"
+#include "chm_host.h"
+#include "chm_internal.h"
+
+namespace chm {
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
+
+namespace {
+
+constexpr int kSaoWG = 256;
+constexpr int kSaoWaves = kSaoWG / 64;
+constexpr int kSaoMaxN = 8;
+constexpr int kSaoGrid = 256;
+constexpr int64_t kSaoCoordLimit = int64_t(1) << 30;
+constexpr int64_t kSaoSqrtMax = 3037000499LL;  // floor(sqrt(2^63 - 1))
+
+struct SaoPair {
+  const int32_t* kq;  // query keypoints (x, y) per row
+  const int32_t* kd;  // db keypoints
+  int32_t nq, nd;
+  int64_t off;        // first query row's position in the match arrays
+};
+
+struct SaoArgs {
+  const SaoPair* pairs;
+  int32_t n_pairs;
+  int32_t n_max;      // rows of the largest query image (slab capacity)
+  const int32_t* match;
+  int32_t* out;
+  int32_t* ced;       // may be null
+  int32_t nn, num, den;
+  uint8_t* slabs;
+  uint64_t slab_bytes;
+  int32_t* errors;
+};
+
+__host__ __device__ inline uint64_t round16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
+__host__ __device__ inline int64_t sao_cells_max(int64_t n) { return 4 * n + 64; }
+
+// Slab layout for capacity n: rows[n], pts[n] (int4: x, y, compact index),
+// cell[C + 1], cell_of[n], nbr_p[8 n], nbr_q[8 n].
+struct Slab {
+  int32_t* rows;
+  int4* pts;
+  int32_t* cell;
+  int32_t* cell_of;
+  int32_t* nbr[2];
+};
+
+__host__ __device__ inline uint64_t slab_bytes(int64_t n) {
+  const int64_t C = sao_cells_max(n);
+  return round16(4 * n) + round16(16 * n) + round16(4 * (C + 1)) + round16(4 * n) +
+         2 * round16(4 * kSaoMaxN * n);
+}
+
+__device__ inline Slab slab_at(uint8_t* base, int64_t n) {
+  Slab s;
+  const int64_t C = sao_cells_max(n);
+  uint8_t* p = base;
+  s.rows = reinterpret_cast<int32_t*>(p);
+  p += round16(4 * n);
+  s.pts = reinterpret_cast<int4*>(p);
+  p += round16(16 * n);
+  s.cell = reinterpret_cast<int32_t*>(p);
+  p += round16(4 * (C + 1));
+  s.cell_of = reinterpret_cast<int32_t*>(p);
+  p += round16(4 * n);
+  s.nbr[0] = reinterpret_cast<int32_t*>(p);
+  p += round16(4 * kSaoMaxN * n);
+  s.nbr[1] = reinterpret_cast<int32_t*>(p);
+  return s;
+}
+
+// Exclusive prefix of v over the work-group; *total receives the sum.
+__device__ inline int block_exclusive(int v, int* s_tmp, int* total) {
+  const int lane = __lane_id(), wave = threadIdx.x >> 6;
+  int incl = v;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int u = __shfl_up(incl, d);
+    if (lane >= d) incl += u;
+  }
+  if (lane == 63) s_tmp[wave] = incl;
+  __syncthreads();
+  int before = 0, sum = 0;
+#pragma unroll
+  for (int w = 0; w < kSaoWaves; ++w) {
+    const int t = s_tmp[w];
+    before += w < wave ? t : 0;
+    sum += t;
+  }
+  __syncthreads();
+  *total = sum;
+  return before + incl - v;
+}
+
+// Barrier between phases that hand data through global memory (plain
+// stores and L2 atomics of other waves of the work-group): the release
+// completes this wave's writes, and the agent-scope acquire invalidates the
+// CU's L1, so no wave reads a line cached before the phase.
+__device__ inline void phase_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+  __builtin_amdgcn_s_waitcnt(0);  // this wave's stores and atomics have completed
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+}
+
+__device__ inline bool lex_less(uint64_t d1, int32_t i1, uint64_t d2, int32_t i2) {
+  return d1 < d2 || (d1 == d2 && i1 < i2);
+}
+
+// The 8 nearest candidates seen so far, ascending by (squared distance,
+// compact index); empty slots hold (UINT64_MAX, INT32_MAX).
+struct NearList {
+  uint64_t d[kSaoMaxN];
+  int32_t i[kSaoMaxN];
+};
+
+__device__ inline void near_insert(NearList& L, uint64_t d, int32_t idx) {
+  if (!lex_less(d, idx, L.d[kSaoMaxN - 1], L.i[kSaoMaxN - 1])) return;
+  bool lt[kSaoMaxN];
+#pragma unroll
+  for (int k = 0; k < kSaoMaxN; ++k) lt[k] = lex_less(d, idx, L.d[k], L.i[k]);
+#pragma unroll
+  for (int k = kSaoMaxN - 1; k >= 1; --k) {
+    if (lt[k]) {
+      L.d[k] = lt[k - 1] ? L.d[k - 1] : d;
+      L.i[k] = lt[k - 1] ? L.i[k - 1] : idx;
+    }
+  }
+  if (lt[0]) {
+    L.d[0] = d;
+    L.i[0] = idx;
+  }
+}
+
+struct GridInfo {
+  int64_t x0, y0, cell, nx, ny;
+};
+
+// The n nearest other points of compact point c (at x, y).
+__device__ inline void ring_search(const Slab& S, const GridInfo& g, int64_t x, int64_t y, int32_t c,
+                                   int n, NearList& L) {
+#pragma unroll
+  for (int k = 0; k < kSaoMaxN; ++k) {
+    L.d[k] = ~uint64_t(0);
+    L.i[k] = INT32_MAX;
+  }
+  const int64_t ix = min(max((x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
+  const int64_t iy = min(max((y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
+  const int64_t rmax = max(max(ix, g.nx - 1 - ix), max(iy, g.ny - 1 - iy));
+  int found = 0;
+  for (int64_t r = 0; r <= rmax; ++r) {
+    for (int64_t j = max(iy - r, int64_t(0)); j <= min(iy + r, g.ny - 1); ++j) {
+      const bool edge = r == 0 || j == iy - r || j == iy + r;
+      const int64_t step = edge ? 1 : 2 * r;
+      for (int64_t i = ix - r; i <= ix + r; i += step) {
+        if (i < 0 || i >= g.nx) continue;
+        const int64_t cid = j * g.nx + i;
+        const int32_t b = cid ? S.cell[cid - 1] : 0, e = S.cell[cid];
+        for (int32_t k = b; k < e; ++k) {
+          const int4 p = S.pts[k];
+          if (p.z == c) continue;
+          const int64_t dx = (int64_t)p.x - x, dy = (int64_t)p.y - y;
+          near_insert(L, (uint64_t)(dx * dx + dy * dy), p.z);
+          ++found;
+        }
+      }
+    }
+    if (found >= n) {
+      uint64_t worst = 0;
+#pragma unroll
+      for (int k = 0; k < kSaoMaxN; ++k)
+        if (k == n - 1) worst = L.d[k];
+      const int64_t lb = r * g.cell;
+      if (lb > kSaoSqrtMax || (uint64_t)(lb * lb) >= worst) break;
+    }
+  }
+}
+
+struct Polar {
+  int32_t dx, dy;
+  uint64_t d2;
+  int32_t label;
+};
+
+__device__ inline int half_plane(int32_t dx, int32_t dy) {
+  if (dx == 0 && dy == 0) return -1;
+  return (dy > 0 || (dy == 0 && dx > 0)) ? 0 : 1;
+}
+
+__device__ inline bool angle_less(const Polar& u, const Polar& v) {
+  const int hu = half_plane(u.dx, u.dy), hv = half_plane(v.dx, v.dy);
+  if (hu != hv) return hu < hv;
+  if (hu >= 0) {
+    const int64_t cross = (int64_t)u.dx * v.dy - (int64_t)u.dy * v.dx;
+    if (cross != 0) return cross > 0;
+  }
+  if (u.d2 != v.d2) return u.d2 < v.d2;
+  return u.label < v.label;
+}
+
+// Sorts the first n entries by angle (odd-even transposition, fixed indices).
+__device__ inline void sort_by_angle(Polar (&e)[kSaoMaxN], int n) {
+#pragma unroll
+  for (int pass = 0; pass < kSaoMaxN; ++pass) {
+#pragma unroll
+    for (int j = pass & 1; j + 1 < kSaoMaxN; j += 2) {
+      if (j + 1 < n && angle_less(e[j + 1], e[j])) {
+        const Polar t = e[j];
+        e[j] = e[j + 1];
+        e[j + 1] = t;
+      }
+    }
+  }
+}
+
+// Least Levenshtein distance between a and the rotations of b (length n).
+__device__ inline int cyclic_edit_distance(const int32_t (&a)[kSaoMaxN], int32_t (&b)[kSaoMaxN], int n) {
+  int best = n;
+#pragma unroll 1
+  for (int s = 0; s < n; ++s) {
+    int row[kSaoMaxN + 1];
+#pragma unroll
+    for (int j = 0; j <= kSaoMaxN; ++j) row[j] = j;
+#pragma unroll
+    for (int i = 1; i <= kSaoMaxN; ++i) {
+      if (i <= n) {
+        int diag = row[0];
+        row[0] = i;
+#pragma unroll
+        for (int j = 1; j <= kSaoMaxN; ++j) {
+          if (j <= n) {
+            const int up = row[j];
+            row[j] = min(min(up + 1, row[j - 1] + 1), diag + (a[i - 1] != b[j - 1] ? 1 : 0));
+            diag = up;
+          }
+        }
+      }
+    }
+    int dist = 0;
+#pragma unroll
+    for (int j = 0; j <= kSaoMaxN; ++j)
+      if (j == n) dist = row[j];
+    best = min(best, dist);
+    const int32_t first = b[0];  // rotate the first n entries left by one
+#pragma unroll
+    for (int k = 0; k + 1 < kSaoMaxN; ++k)
+      if (k + 1 < n) b[k] = b[k + 1];
+      else if (k + 1 == n) b[k] = first;
+    if (n == kSaoMaxN) b[kSaoMaxN - 1] = first;
+  }
+  return best;
+}
+
+__device__ inline int2 point_of(const SaoArgs& a, const SaoPair& P, const Slab& S, int side, int32_t c) {
+  const int32_t row = S.rows[c];
+  if (side == 0) return make_int2(P.kq[2 * (int64_t)row], P.kq[2 * (int64_t)row + 1]);
+  const int32_t m = a.match[P.off + row];  // validated during compaction
+  return make_int2(P.kd[2 * (int64_t)m], P.kd[2 * (int64_t)m + 1]);
+}
+
+__global__ __launch_bounds__(kSaoWG) void k_sao(SaoArgs a) {
+  __shared__ int s_tmp[kSaoWaves];
+  __shared__ int s_M, s_bad;
+  __shared__ int s_red[4][kSaoWaves];
+  __shared__ GridInfo s_grid;
+  const Slab S = slab_at(a.slabs + a.slab_bytes * blockIdx.x, a.n_max);
+  const int tid = threadIdx.x;
+
+  for (int p = blockIdx.x; p < a.n_pairs; p += gridDim.x) {
+    const SaoPair P = a.pairs[p];
+    const int nq = min(max(P.nq, 0), a.n_max);
+    if (tid == 0) {
+      s_M = 0;
+      s_bad = P.nq > a.n_max || P.nq < 0 ? 1 : 0;
+    }
+    phase_barrier();
+    // 1. compaction of the matched rows (and the outputs start at -1)
+    for (int base = 0; base < nq; base += kSaoWG) {
+      const int i = base + tid;
+      int32_t m = -1;
+      if (i < nq) {
+        m = a.match[P.off + i];
+        a.out[P.off + i] = -1;
+        if (a.ced) a.ced[P.off + i] = -1;
+        if (m >= P.nd) s_bad = 1;
+      }
+      const int flag = (m >= 0 && m < P.nd) ? 1 : 0;
+      int total;
+      const int pos = block_exclusive(flag, s_tmp, &total);
+      if (flag) S.rows[s_M + pos] = i;
+      phase_barrier();
+      if (tid == 0) s_M += total;
+      phase_barrier();
+    }
+    const int M = s_M;
+    const int n = M > 0 ? min(a.nn, M - 1) : 0;
+
+    // 2. per image: grid, then the N nearest of every match
+    for (int side = 0; side < 2 && n > 0; ++side) {
+      int32_t* nbr = side ? S.nbr[1] : S.nbr[0];
+      int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
+      for (int c = tid; c < M; c += kSaoWG) {
+        const int2 q = point_of(a, P, S, side, c);
+        if (q.x <= -kSaoCoordLimit || q.x >= kSaoCoordLimit || q.y <= -kSaoCoordLimit || q.y >= kSaoCoordLimit)
+          s_bad = 1;
+        xmin = min(xmin, q.x);
+        ymin = min(ymin, q.y);
+        xmax = max(xmax, q.x);
+        ymax = max(ymax, q.y);
+      }
+#pragma unroll
+      for (int d = 32; d >= 1; d >>= 1) {
+        xmin = min(xmin, __shfl_xor(xmin, d));
+        ymin = min(ymin, __shfl_xor(ymin, d));
+        xmax = max(xmax, __shfl_xor(xmax, d));
+        ymax = max(ymax, __shfl_xor(ymax, d));
+      }
+      if (__lane_id() == 0) {
+        s_red[0][tid >> 6] = xmin;
+        s_red[1][tid >> 6] = ymin;
+        s_red[2][tid >> 6] = xmax;
+        s_red[3][tid >> 6] = ymax;
+      }
+      phase_barrier();
+      if (tid == 0) {
+        int64_t x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+        for (int w = 0; w < kSaoWaves; ++w) {
+          x0 = min(x0, (int64_t)s_red[0][w]);
+          y0 = min(y0, (int64_t)s_red[1][w]);
+          x1 = max(x1, (int64_t)s_red[2][w]);
+          y1 = max(y1, (int64_t)s_red[3][w]);
+        }
+        const double w = double(x1 - x0) + 1.0, h = double(y1 - y0) + 1.0;
+        int64_t cell = max(int64_t(1), (int64_t)ceil(sqrt(w * h * 2.0 / double(M))));
+        int64_t nx, ny;
+        for (;;) {  // at most 4 M + 64 cells, so the cell array always fits
+          nx = (x1 - x0) / cell + 1;
+          ny = (y1 - y0) / cell + 1;
+          if ((double)nx * (double)ny <= 4.0 * (double)M + 64.0) break;
+          cell *= 2;
+        }
+        s_grid = GridInfo{x0, y0, cell, nx, ny};
+      }
+      phase_barrier();
+      const GridInfo g = s_grid;
+      const int64_t ncell = g.nx * g.ny;
+      for (int64_t k = tid; k <= ncell; k += kSaoWG) S.cell[k] = 0;
+      phase_barrier();
+      for (int c = tid; c < M; c += kSaoWG) {
+        const int2 q = point_of(a, P, S, side, c);
+        const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
+        const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
+        const int32_t cid = (int32_t)(cy * g.nx + cx);
+        S.cell_of[c] = cid;
+        atomicAdd(&S.cell[cid], 1);
+      }
+      phase_barrier();
+      // exclusive scan: cell[k] = first slot of cell k
+      int run = 0;
+      for (int64_t base = 0; base < ncell; base += kSaoWG) {
+        const int64_t k = base + tid;
+        const int v = k < ncell ? S.cell[k] : 0;
+        int total;
+        const int ex = block_exclusive(v, s_tmp, &total);
+        if (k < ncell) S.cell[k] = run + ex;
+        run += total;
+      }
+      phase_barrier();
+      // scatter; afterwards cell[k] is the end of cell k (= start of k + 1)
+      for (int c = tid; c < M; c += kSaoWG) {
+        const int2 q = point_of(a, P, S, side, c);
+        const int32_t slot = atomicAdd(&S.cell[S.cell_of[c]], 1);
+        S.pts[min(max(slot, 0), M - 1)] = make_int4(q.x, q.y, c, 0);
+      }
+      phase_barrier();
+      for (int c = tid; c < M; c += kSaoWG) {
+        const int2 q = point_of(a, P, S, side, c);
+        NearList L;
+        ring_search(S, g, q.x, q.y, c, n, L);
+#pragma unroll
+        for (int k = 0; k < kSaoMaxN; ++k)
+          if (k < n) nbr[(int64_t)c * kSaoMaxN + k] = min(max(L.i[k], 0), M - 1);
+      }
+      phase_barrier();
+    }
+
+    // 3. angular orders, cyclic edit distance, verdict
+    const bool bad = s_bad != 0;
+    for (int c = tid; c < M && !bad; c += kSaoWG) {
+      const int32_t row = S.rows[c];
+      const int32_t m = a.match[P.off + row];
+      int dist = 0;
+      if (n > 0) {
+        int32_t lab[2][kSaoMaxN];
+#pragma unroll
+        for (int side = 0; side < 2; ++side) {
+          const int2 o = point_of(a, P, S, side, c);
+          Polar e[kSaoMaxN];
+#pragma unroll
+          for (int k = 0; k < kSaoMaxN; ++k) {
+            const int32_t nb = k < n ? (side ? S.nbr[1] : S.nbr[0])[(int64_t)c * kSaoMaxN + k] : c;
+            const int2 q = point_of(a, P, S, side, nb);
+            const int32_t dx = q.x - o.x, dy = q.y - o.y;
+            e[k] = Polar{dx, dy, (uint64_t)((int64_t)dx * dx + (int64_t)dy * dy), nb};
+          }
+          sort_by_angle(e, n);
+#pragma unroll
+          for (int k = 0; k < kSaoMaxN; ++k) lab[side][k] = e[k].label;
+        }
+        dist = cyclic_edit_distance(lab[0], lab[1], n);
+      }
+      if ((int64_t)dist * a.den <= (int64_t)a.num * n) a.out[P.off + row] = m;
+      if (a.ced) a.ced[P.off + row] = dist;
+    }
+    if (tid == 0 && bad) atomicAdd(a.errors, 1);
+    phase_barrier();
+  }
+}
+
+}  // namespace
+
+static uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows) {
+  const int64_t G = std::min<int64_t>(std::max(n_pairs, 1), kSaoGrid);
+  return 256 + round16(sizeof(SaoPair) * (uint64_t)std::max(n_pairs, 1)) +
+         (uint64_t)G * slab_bytes(std::max(max_rows, 1));
+}
+
+static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match,
+                      int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
+                      hipStream_t s) {
+  int32_t n_max = 1;
+  std::vector<SaoPair> hp((size_t)n_pairs);
+  for (int32_t p = 0; p < n_pairs; ++p) {
+    const int32_t q = h_pairs[2 * p], d = h_pairs[2 * p + 1];
+    hp[(size_t)p] = SaoPair{d_kp[q], d_kp[d], h_n_feats[q], h_n_feats[d], h_offs[p]};
+    n_max = std::max(n_max, h_n_feats[q]);
+  }
+  uint8_t* w = static_cast<uint8_t*>(d_work);
+  SaoPair* dp = reinterpret_cast<SaoPair*>(w + 256);
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, 1, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), sizeof(SaoPair) * hp.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // hp is freed on return
+  if (e != hipSuccess) return e;
+  SaoArgs a;
+  a.pairs = dp;
+  a.n_pairs = n_pairs;
+  a.n_max = n_max;
+  a.match = d_match;
+  a.out = d_out;
+  a.ced = d_ced;
+  a.nn = nn;
+  a.num = num;
+  a.den = den;
+  a.slabs = w + 256 + round16(sizeof(SaoPair) * (uint64_t)n_pairs);
+  a.slab_bytes = slab_bytes(n_max);
+  a.errors = reinterpret_cast<int32_t*>(w);
+  const int grid = std::min(n_pairs, kSaoGrid);
+  hipLaunchKernelGGL(k_sao, dim3(grid), dim3(kSaoWG), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace chm
+
+extern "C" chm_status chm_sao_work_bytes(int32_t n_pairs, int32_t max_query_rows, uint64_t* out_bytes) {
+  chm::clear_error();
+  if (!out_bytes || n_pairs < 0 || max_query_rows < 0) return chm::fail(CHM_E_INVALID_ARG, "bad arguments");
+  *out_bytes = chm::sao_work_bytes(n_pairs, max_query_rows);
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_sao_filter_device(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                                            const int32_t* h_n_feats, int32_t n_images, const int64_t* h_offs,
+                                            const int32_t* d_match, int32_t n_neighbors, int32_t score_num,
+                                            int32_t score_den, int32_t* d_out, int32_t* d_ced, void* d_work,
+                                            uint64_t work_bytes, void* stream) {
+  using namespace chm;
+  clear_error();
+  if (n_pairs < 0 || n_images < 0) return fail(CHM_E_INVALID_ARG, "negative count");
+  if (n_pairs == 0) return CHM_OK;
+  if (!h_pairs || !d_kp || !h_n_feats || !h_offs || !d_match || !d_out || !d_work)
+    return fail(CHM_E_INVALID_ARG, "NULL array");
+  if (n_neighbors < 1 || n_neighbors > kSaoMaxN)
+    return fail(CHM_E_INVALID_ARG, "n_neighbors must be 1..%d on the device", kSaoMaxN);
+  if (score_num < 0 || score_den <= 0) return fail(CHM_E_INVALID_ARG, "bad score threshold");
+  if (d_out == d_match || (d_ced && (const int32_t*)d_ced == d_match))
+    return fail(CHM_E_INVALID_ARG, "d_out and d_ced must not be d_match");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256) return fail(CHM_E_INVALID_ARG, "d_work must be 256-byte aligned");
+  int32_t n_max = 0;
+  for (int32_t p = 0; p < n_pairs; ++p) {
+    const int32_t q = h_pairs[2 * p], d = h_pairs[2 * p + 1];
+    if (q < 0 || q >= n_images || d < 0 || d >= n_images)
+      return fail(CHM_E_INVALID_ARG, "pair %d names an image outside 0..%d", p, n_images - 1);
+    if (h_n_feats[q] < 0 || h_n_feats[d] < 0) return fail(CHM_E_INVALID_ARG, "negative row count");
+    if ((h_n_feats[q] > 0 && !d_kp[q]) || (h_n_feats[d] > 0 && !d_kp[d]))
+      return fail(CHM_E_INVALID_ARG, "pair %d: NULL keypoints", p);
+    if (h_offs[p] < 0 || h_offs[p + 1] - h_offs[p] != h_n_feats[q])
+      return fail(CHM_E_INVALID_ARG, "pair %d: offsets do not span the query image's rows", p);
+    n_max = std::max(n_max, h_n_feats[q]);
+  }
+  const uint64_t need = sao_work_bytes(n_pairs, n_max);
+  if (work_bytes < need)
+    return fail(CHM_E_CAPACITY, "work buffer holds %llu bytes, %llu needed", (unsigned long long)work_bytes,
+                (unsigned long long)need);
+  const hipError_t e = launch_sao(n_pairs, h_pairs, d_kp, h_n_feats, h_offs, d_match, n_neighbors, score_num,
+                                  score_den, d_out, d_ced, d_work, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
+  return CHM_OK;
+}

@@ -1,0 +1,138 @@
+"""SAO on the device against the oracle (and the host implementation,
+itself equal to the oracle), bit for bit: CED per match and the filtered
+matches."""
+import numpy as np
+import pytest
+
+from oracle import sao as S
+from paper_2505_22089_amd import chm, synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+from tests.gpu_helpers import load_all, new_store, run_match  # noqa: E402
+
+
+def _dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _similar(pts, quarter_turns, shift):
+    x, y = pts[:, 0].astype(np.int64), pts[:, 1].astype(np.int64)
+    for _ in range(quarter_turns):
+        x, y = -y, x
+    return np.stack([x + shift[0], y + shift[1]], axis=1)
+
+
+def _pair_case(seed, n_q=300, n_d=280, frac=0.6, outliers=0.25, dup=0.05, spread=30000):
+    rng = np.random.default_rng(seed)
+    kq = rng.integers(0, spread, size=(n_q, 2)).astype(np.int32)
+    kd = rng.integers(-spread, spread, size=(n_d, 2)).astype(np.int32)
+    match = np.where(rng.random(n_q) < frac, rng.integers(0, n_d, n_q), -1).astype(np.int32)
+    good = (match >= 0) & (rng.random(n_q) >= outliers)
+    kd[match[good]] = _similar(kq[good], 1, (5, 7)).astype(np.int32)
+    d = (match >= 0) & (rng.random(n_q) < dup)
+    if d.any() and (match >= 0).any():
+        match[d] = match[match >= 0][0]
+    return kq, kd, match
+
+
+def _run_device(kps, pairs, offs, match, nn, th):
+    out = torch.full((len(match),), -7, dtype=torch.int32, device="cuda")
+    ced = torch.full((len(match),), -7, dtype=torch.int32, device="cuda")
+    work = chm.sao_filter_device([_dev(k) for k in kps], pairs, offs, _dev(match), out, ced,
+                                 n_neighbors=nn, threshold=th)
+    torch.cuda.synchronize()
+    return out.cpu().numpy(), ced.cpu().numpy(), chm.sao_input_errors(work)
+
+
+@pytest.mark.parametrize("nn,th", [(6, (1, 2)), (1, (0, 1)), (8, (1, 3)), (3, (2, 3))])
+def test_device_sao_matches_oracle(nn, th):
+    cases = [_pair_case(s) for s in range(4)]
+    cases.append(_pair_case(9, n_q=40, frac=0.05))            # a handful of matches
+    cases.append(_pair_case(10, n_q=50, frac=0.0))            # none
+    cases.append(_pair_case(11, n_q=20, frac=0.1))            # one or two
+    cases.append(_pair_case(12, n_q=700, n_d=60, frac=0.9, dup=0.3))  # many shared db rows
+    kps, pairs, parts = [], [], []
+    for kq, kd, m in cases:
+        pairs.append((len(kps), len(kps) + 1))
+        kps += [kq, kd]
+        parts.append(m)
+    offs = np.concatenate([[0], np.cumsum([len(m) for m in parts])]).astype(np.int64)
+    out, ced, bad = _run_device(kps, np.array(pairs), offs, np.concatenate(parts), nn, th)
+    assert bad == 0
+    for p, (kq, kd, m) in enumerate(cases):
+        rc, rf = S.sao_pair(kq, kd, m, nn, th)
+        assert np.array_equal(ced[offs[p]:offs[p + 1]], rc), p
+        assert np.array_equal(out[offs[p]:offs[p + 1]], rf), p
+
+
+def test_device_sao_degenerate_layouts():
+    # collinear points, all points on one spot, a thin strip, huge spread
+    rng = np.random.default_rng(20)
+    n = 200
+    layouts = [np.stack([np.arange(n) * 7, np.zeros(n)], 1),
+               np.full((n, 2), 12345),
+               np.stack([rng.integers(0, 1 << 29, n), rng.integers(0, 3, n)], 1),
+               rng.integers(-(1 << 29), 1 << 29, size=(n, 2))]
+    kps, pairs, parts = [], [], []
+    for lay in layouts:
+        kq = lay.astype(np.int32)
+        kd = _similar(kq, 3, (-11, 4)).astype(np.int32)
+        m = np.arange(n, dtype=np.int32)
+        m[rng.random(n) < 0.2] = -1
+        pairs.append((len(kps), len(kps) + 1))
+        kps += [kq, kd]
+        parts.append(m)
+    offs = np.concatenate([[0], np.cumsum([len(m) for m in parts])]).astype(np.int64)
+    out, ced, bad = _run_device(kps, np.array(pairs), offs, np.concatenate(parts), 6, (1, 2))
+    assert bad == 0
+    for p, (m) in enumerate(parts):
+        rc, rf = S.sao_pair(kps[2 * p], kps[2 * p + 1], m, 6, (1, 2))
+        assert np.array_equal(ced[offs[p]:offs[p + 1]], rc), p
+        assert np.array_equal(out[offs[p]:offs[p + 1]], rf), p
+
+
+def test_device_sao_counts_broken_pairs_and_keeps_the_rest():
+    kq, kd, m = _pair_case(30)
+    bad_m = m.copy()
+    bad_m[np.argmax(bad_m >= 0)] = len(kd) + 5  # a db row outside the db image
+    far = kq.copy()
+    far[np.argmax(m >= 0)] = (1 << 30, 0)       # a coordinate out of range
+    kps = [kq, kd, far]
+    pairs = np.array([[0, 1], [0, 1], [2, 1]])
+    parts = [m, bad_m, m]
+    offs = np.concatenate([[0], np.cumsum([len(x) for x in parts])]).astype(np.int64)
+    out, ced, bad = _run_device(kps, pairs, offs, np.concatenate(parts), 6, (1, 2))
+    assert bad == 2
+    rc, rf = S.sao_pair(kq, kd, m, 6, (1, 2))
+    assert np.array_equal(ced[offs[0]:offs[1]], rc) and np.array_equal(out[offs[0]:offs[1]], rf)
+    assert (out[offs[1]:] == -1).all()
+
+
+def test_device_sao_on_matcher_output_with_repeated_texture():
+    """The GPU matcher's output of a repeated-texture workload: device SAO
+    equals the host implementation on every pair and the oracle on sampled
+    matches."""
+    wl = synth.config2(n_images=10, n_feats=3000, k=4, repeat_frac=0.3)
+    kps = synth.keypoints(wl)
+    st = new_store(wl)
+    load_all(st, wl.images)
+    out, _, offs = run_match(st, wl.pairs)
+    st.close()
+    d_out = torch.empty(len(out), dtype=torch.int32, device="cuda")
+    d_ced = torch.empty(len(out), dtype=torch.int32, device="cuda")
+    work = chm.sao_filter_device([_dev(k) for k in kps], wl.pairs, offs, _dev(out), d_out, d_ced)
+    assert chm.sao_input_errors(work) == 0
+    g_out, g_ced = d_out.cpu().numpy(), d_ced.cpu().numpy()
+    h_out, h_ced = chm.sao_filter(kps, wl.pairs, offs, out, 6, (1, 2), want_ced=True)
+    assert np.array_equal(g_ced, h_ced) and np.array_equal(g_out, h_out)
+    rng = np.random.default_rng(1)
+    for p in rng.choice(len(wl.pairs), 3, replace=False):
+        q, d = wl.pairs[p]
+        m = out[offs[p]:offs[p + 1]]
+        rows = rng.choice(np.nonzero(m >= 0)[0], 40, replace=False)
+        rc, rf = S.sao_pair(kps[q], kps[d], m, 6, (1, 2), only_rows=rows)
+        assert np.array_equal(g_ced[offs[p] + rows], rc[rows])
+        assert np.array_equal(g_out[offs[p] + rows], rf[rows])
+    assert (g_ced[out < 0] == -1).all() and (g_out[out < 0] == -1).all()

@@ -209,3 +209,26 @@ def test_library_rejects_bad_input():
         chm.sao_filter([kq, kd], pairs, np.array([0, len(m) - 1], np.int64), m[:-1])
     with pytest.raises(chm.ChmError, match="image"):
         chm.sao_filter([kq, kd], np.array([[0, 2]]), offs, m)
+
+
+def test_device_entry_rejects_bad_arguments_before_any_gpu_call():
+    """Argument checks of chm_sao_filter_device run on the host and return
+    before anything is enqueued (no device is needed to see them)."""
+    L = chm.lib()
+    pairs = np.array([[0, 1]], np.int32)
+    nf = np.array([10, 10], np.int32)
+    offs = np.array([0, 10], np.int64)
+    fake = (C.c_void_p * 2)(256, 512)  # never dereferenced on these paths
+    kp = C.cast(fake, C.c_void_p)
+
+    def call(nn=6, num=1, den=2, match=4096, out=8192, work=1 << 20, work_bytes=1 << 30, offsets=offs):
+        return L.chm_sao_filter_device(1, pairs.ctypes.data, kp, nf.ctypes.data, 2, offsets.ctypes.data,
+                                       match, nn, num, den, out, None, work, work_bytes, None)
+    assert call(nn=9) == -1
+    assert call(den=0) == -1
+    assert call(out=4096) == -1                        # output aliases the matches
+    assert call(work=(1 << 20) + 16) == -1             # misaligned work buffer
+    assert call(offsets=np.array([0, 9], np.int64)) == -1
+    need = chm.sao_work_bytes(1, 10)
+    assert call(work_bytes=need - 1) == -3             # CHM_E_CAPACITY
+    assert chm.sao_work_bytes(400, 8000) < (1 << 30)
