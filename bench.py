@@ -240,6 +240,9 @@ def main():
 
     if args.workload == "knn-200x40000":
         res["bruteforce"] = bruteforce_leg(wl, descs, stream)
+    if not args.profile:
+        print("[bench] SAO leg", file=sys.stderr, flush=True)
+        res["sao"] = sao_leg(wl, out_b, offs, stream, host_pairs=None if args.workload != "knn-200x40000" else 50)
     if not args.no_cpu:
         print("[bench] cpu baseline", file=sys.stderr, flush=True)
         if args.workload == "knn-50x8000":
@@ -274,6 +277,48 @@ def cpu_baseline(wl, gpu_out, min_seconds=10.0, max_reps=8):
             "sample": "the whole step (hash %d images + match all %d pairs) run %d times: %.1f s hashing, "
                       "%.1f s matching" % (len(wl.images), P, reps, t_hash, t_match),
             "gpu_identical_all_pairs": same}
+
+
+def sao_leg(wl, out_b, offs, stream, reps=10, n_neighbors=6, threshold=(1, 2), host_pairs=None):
+    """SAO local constraint (Sec. 2.3.3) on the batched matcher's output: the
+    device kernel (keypoints resident in HBM, HIP events on the stream) and
+    the host implementation on all hardware threads, over all pairs (or the
+    first host_pairs), with their outputs compared."""
+    import os
+    import torch
+
+    from paper_2505_22089_amd import chm, synth
+    kps = synth.keypoints(wl)
+    d_kps = [torch.from_numpy(k).to(out_b.device) for k in kps]
+    nmax = int(max(wl.images[q].shape[0] for q in wl.pairs[:, 0]))
+    work = torch.empty(chm.sao_work_bytes(len(wl.pairs), nmax) + 256, dtype=torch.uint8, device=out_b.device)
+    work = work[(-work.data_ptr()) % 256:]
+    d_out = torch.empty_like(out_b)
+    with torch.cuda.stream(stream):
+        chm.sao_filter_device(d_kps, wl.pairs, offs, out_b, d_out, None, work, n_neighbors, threshold, stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            chm.sao_filter_device(d_kps, wl.pairs, offs, out_b, d_out, None, work, n_neighbors, threshold,
+                                  stream)
+        b.record(stream)
+    stream.synchronize()
+    dev_ms = a.elapsed_time(b) / reps
+    bad = chm.sao_input_errors(work)
+    g = d_out.cpu().numpy()
+    m = out_b.cpu().numpy()
+    P = len(wl.pairs) if host_pairs is None else min(host_pairs, len(wl.pairs))
+    end = int(offs[P])
+    threads = os.cpu_count() or 1
+    t0 = time.perf_counter()
+    h = chm.sao_filter(kps, wl.pairs[:P], offs[:P + 1], m[:end], n_neighbors, threshold, n_threads=threads)
+    host_s = time.perf_counter() - t0
+    return {"n_neighbors": n_neighbors, "threshold": "%d/%d" % threshold,
+            "device_ms": round(dev_ms, 4), "device_pairs_per_s": round(len(wl.pairs) / (dev_ms * 1e-3), 1),
+            "matches_in": int((m >= 0).sum()), "kept": int((g >= 0).sum()), "input_errors": bad,
+            "host_pairs": P, "host_threads": threads, "host_ms": round(host_s * 1e3, 1),
+            "host_pairs_per_s": round(P / host_s, 1),
+            "device_equals_host": bool(np.array_equal(g[:end], h))}
 
 
 def bruteforce_leg(wl, descs, stream, reps=5):

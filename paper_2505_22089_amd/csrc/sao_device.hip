@@ -1,20 +1,19 @@
 // SAO local geometric constraint (Sec. 2.3.3, Fig. 4) on the device: the same
 // scores as the host implementation, for up to 8 neighbours.
 //
-// One work-group per pair (grid-stride over the pairs), each with its own
-// scratch slab in the caller's work buffer:
-//  1. the pair's matched query rows are compacted in row order (a block scan
-//     of the match flags), so a compact index orders like the query row that
-//     labels the match;
-//  2. for the query image and then the db image, the matched keypoints are
-//     counting-sorted into a uniform grid (about two points per cell), and
-//     every match finds its N nearest other matches by an exact ring search
-//     over the cells (64-bit squared distances, ties by compact index),
-//     stopping once the next ring's distance bound reaches the N-th distance;
-//  3. each match sorts its two neighbour lists by angle (half-plane, then
-//     the sign of a 64-bit cross product) and takes the cyclic edit distance
-//     of the two label sequences as the least Levenshtein distance over the
-//     rotations of one of them (Maes, 1990).
+// Pairs go in batches, each with its own scratch in the caller's work buffer.
+//  1. k_sao_build, one work-group per pair: the matched query rows are
+//     compacted in row order (a block scan of the match flags), so a compact
+//     index orders like the query row that labels the match; then, for the
+//     query image and for the db image, the matched keypoints are
+//     counting-sorted into a uniform grid of about two points per cell.
+//  2. k_sao_search, one thread per match: in each image an exact ring
+//     search over the cells finds the N nearest other matches (64-bit
+//     squared distances, ties by compact index), stopping once the next
+//     ring's distance bound reaches the N-th distance; the two neighbour
+//     lists are sorted by angle (half-plane, then the sign of a 64-bit cross
+//     product) and their labels compared by the cyclic edit distance, the
+//     least Levenshtein distance over the rotations of one list (Maes, 1990).
 // All geometry is exact for coordinates below 2^30 in magnitude.  A pair
 // whose input breaks the contract (a db row outside the db image, or a
 // coordinate out of range) keeps no match and is counted in the first word
@@ -32,10 +31,11 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
 
 namespace {
 
-constexpr int kSaoWG = 256;
-constexpr int kSaoWaves = kSaoWG / 64;
+constexpr int kSaoWG = 256;                        // search: one thread per match
+constexpr int kSaoBuildWG = 256;                   // build: one work-group per pair
+constexpr int kSaoBuildWaves = kSaoBuildWG / 64;
 constexpr int kSaoMaxN = 8;
-constexpr int kSaoGrid = 256;
+constexpr int kSaoBatch = 512;  // pairs per launch pair (scratch is per pair)
 constexpr int64_t kSaoCoordLimit = int64_t(1) << 30;
 constexpr int64_t kSaoSqrtMax = 3037000499LL;  // floor(sqrt(2^63 - 1))
 
@@ -46,57 +46,66 @@ struct SaoPair {
   int64_t off;        // first query row's position in the match arrays
 };
 
+struct GridInfo {
+  int64_t x0, y0, cell, nx, ny;
+};
+
+struct PairInfo {  // 128 bytes at the head of a pair's scratch
+  int32_t M, bad, pad0, pad1;
+  GridInfo g[2];
+  int32_t pad[4];
+};
+static_assert(sizeof(PairInfo) <= 128, "pair info fits its 128 bytes");
+
 struct SaoArgs {
-  const SaoPair* pairs;
+  const SaoPair* pairs;  // this batch's pairs
   int32_t n_pairs;
-  int32_t n_max;      // rows of the largest query image (slab capacity)
+  int32_t n_max;         // rows of the largest query image (scratch capacity)
   const int32_t* match;
   int32_t* out;
-  int32_t* ced;       // may be null
+  int32_t* ced;          // may be null
   int32_t nn, num, den;
-  uint8_t* slabs;
-  uint64_t slab_bytes;
+  uint8_t* scratch;
+  uint64_t scratch_bytes;  // per pair
   int32_t* errors;
 };
 
 __host__ __device__ inline uint64_t round16(uint64_t v) { return (v + 15) & ~uint64_t(15); }
 __host__ __device__ inline int64_t sao_cells_max(int64_t n) { return 4 * n + 64; }
 
-// Slab layout for capacity n: rows[n], pts[n] (int4: x, y, compact index),
-// cell[C + 1], cell_of[n], nbr_p[8 n], nbr_q[8 n].
-struct Slab {
+// A pair's scratch for capacity n: info, rows[n], and per image pts[n]
+// (int4: x, y, compact index; in cell order) and cell[C + 1] (cell ends).
+struct PairScratch {
+  PairInfo* info;
   int32_t* rows;
-  int4* pts;
-  int32_t* cell;
-  int32_t* cell_of;
-  int32_t* nbr[2];
+  int4* pts[2];
+  int32_t* cell[2];
 };
 
-__host__ __device__ inline uint64_t slab_bytes(int64_t n) {
+__host__ __device__ inline uint64_t pair_scratch_bytes(int64_t n) {
   const int64_t C = sao_cells_max(n);
-  return round16(4 * n) + round16(16 * n) + round16(4 * (C + 1)) + round16(4 * n) +
-         2 * round16(4 * kSaoMaxN * n);
+  return 128 + round16(4 * n) + 2 * (round16(16 * n) + round16(4 * (C + 1)));
 }
 
-__device__ inline Slab slab_at(uint8_t* base, int64_t n) {
-  Slab s;
-  const int64_t C = sao_cells_max(n);
-  uint8_t* p = base;
+__device__ inline PairScratch scratch_at(const SaoArgs& a, int pair) {
+  const int64_t n = a.n_max, C = sao_cells_max(n);
+  uint8_t* p = a.scratch + a.scratch_bytes * (uint64_t)pair;
+  PairScratch s;
+  s.info = reinterpret_cast<PairInfo*>(p);
+  p += 128;
   s.rows = reinterpret_cast<int32_t*>(p);
   p += round16(4 * n);
-  s.pts = reinterpret_cast<int4*>(p);
-  p += round16(16 * n);
-  s.cell = reinterpret_cast<int32_t*>(p);
-  p += round16(4 * (C + 1));
-  s.cell_of = reinterpret_cast<int32_t*>(p);
-  p += round16(4 * n);
-  s.nbr[0] = reinterpret_cast<int32_t*>(p);
-  p += round16(4 * kSaoMaxN * n);
-  s.nbr[1] = reinterpret_cast<int32_t*>(p);
+  for (int side = 0; side < 2; ++side) {
+    s.pts[side] = reinterpret_cast<int4*>(p);
+    p += round16(16 * n);
+    s.cell[side] = reinterpret_cast<int32_t*>(p);
+    p += round16(4 * (C + 1));
+  }
   return s;
 }
 
 // Exclusive prefix of v over the work-group; *total receives the sum.
+template <int WAVES>
 __device__ inline int block_exclusive(int v, int* s_tmp, int* total) {
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
   int incl = v;
@@ -109,7 +118,7 @@ __device__ inline int block_exclusive(int v, int* s_tmp, int* total) {
   __syncthreads();
   int before = 0, sum = 0;
 #pragma unroll
-  for (int w = 0; w < kSaoWaves; ++w) {
+  for (int w = 0; w < WAVES; ++w) {
     const int t = s_tmp[w];
     before += w < wave ? t : 0;
     sum += t;
@@ -141,8 +150,8 @@ struct NearList {
   int32_t i[kSaoMaxN];
 };
 
+// Inserts (d, idx), which the caller has checked to be below the n-th entry.
 __device__ inline void near_insert(NearList& L, uint64_t d, int32_t idx) {
-  if (!lex_less(d, idx, L.d[kSaoMaxN - 1], L.i[kSaoMaxN - 1])) return;
   bool lt[kSaoMaxN];
 #pragma unroll
   for (int k = 0; k < kSaoMaxN; ++k) lt[k] = lex_less(d, idx, L.d[k], L.i[k]);
@@ -159,53 +168,99 @@ __device__ inline void near_insert(NearList& L, uint64_t d, int32_t idx) {
   }
 }
 
-struct GridInfo {
-  int64_t x0, y0, cell, nx, ny;
+// A grid in global memory (the build kernel's output).
+struct GlobalGrid {
+  const int32_t* cell;  // cell ends
+  const int4* pts;      // x, y, compact index, in cell order
+  __device__ int32_t end(int64_t cid) const { return cell[cid]; }
+  __device__ int4 pt(int32_t k) const { return pts[k]; }
 };
 
-// The n nearest other points of compact point c (at x, y).
-__device__ inline void ring_search(const Slab& S, const GridInfo& g, int64_t x, int64_t y, int32_t c,
-                                   int n, NearList& L) {
+// The n nearest other points of compact point c (at x, y): their compact
+// indices in out[0..n), ascending by (squared distance, index).  With
+// PACKED (every |dx|, |dy| below 2^23 and indices below 2^16) the two parts
+// travel as one 64-bit key (d2 << 16 | index), which orders the same way.
+template <bool PACKED, class Grid>
+__device__ inline void ring_search(const Grid& G, const GridInfo& g, int64_t x, int64_t y, int32_t c, int n,
+                                   int32_t (&out)[kSaoMaxN]) {
+  NearList L;        // general keys
+  uint64_t K[kSaoMaxN];  // packed keys
 #pragma unroll
   for (int k = 0; k < kSaoMaxN; ++k) {
     L.d[k] = ~uint64_t(0);
     L.i[k] = INT32_MAX;
+    K[k] = ~uint64_t(0);
   }
-  const int64_t ix = min(max((x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
-  const int64_t iy = min(max((y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
-  const int64_t rmax = max(max(ix, g.nx - 1 - ix), max(iy, g.ny - 1 - iy));
+  // cell counts are at most 4 M + 64, so cell coordinates fit 32 bits
+  const int32_t nx = (int32_t)g.nx, ny = (int32_t)g.ny;
+  const int32_t ix = (int32_t)min(max((x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
+  const int32_t iy = (int32_t)min(max((y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
+  const int32_t rmax = max(max(ix, nx - 1 - ix), max(iy, ny - 1 - iy));
+  const int32_t xs = (int32_t)x, ys = (int32_t)y;
+  uint64_t wd = ~uint64_t(0);  // the n-th entry (the last one kept)
+  int32_t wi = INT32_MAX;
+  uint64_t wk = ~uint64_t(0);
   int found = 0;
-  for (int64_t r = 0; r <= rmax; ++r) {
-    for (int64_t j = max(iy - r, int64_t(0)); j <= min(iy + r, g.ny - 1); ++j) {
+  for (int32_t r = 0; r <= rmax; ++r) {
+    for (int32_t j = max(iy - r, 0); j <= min(iy + r, ny - 1); ++j) {
       const bool edge = r == 0 || j == iy - r || j == iy + r;
-      const int64_t step = edge ? 1 : 2 * r;
-      for (int64_t i = ix - r; i <= ix + r; i += step) {
-        if (i < 0 || i >= g.nx) continue;
-        const int64_t cid = j * g.nx + i;
-        const int32_t b = cid ? S.cell[cid - 1] : 0, e = S.cell[cid];
+      const int32_t step = edge ? 1 : 2 * r;
+      for (int32_t i = ix - r; i <= ix + r; i += step) {
+        if (i < 0 || i >= nx) continue;
+        const int32_t cid = j * nx + i;
+        const int32_t b = cid ? G.end(cid - 1) : 0, e = G.end(cid);
         for (int32_t k = b; k < e; ++k) {
-          const int4 p = S.pts[k];
+          const int4 p = G.pt(k);
           if (p.z == c) continue;
-          const int64_t dx = (int64_t)p.x - x, dy = (int64_t)p.y - y;
-          near_insert(L, (uint64_t)(dx * dx + dy * dy), p.z);
+          // |dx|, |dy| < 2^31: squares as 32 x 32 -> 64-bit products
+          const uint32_t ax = (uint32_t)abs(p.x - xs), ay = (uint32_t)abs(p.y - ys);
+          const uint64_t d2 = (uint64_t)ax * ax + (uint64_t)ay * ay;
           ++found;
+          if (PACKED) {
+            const uint64_t key = (d2 << 16) | (uint32_t)p.z;
+            if (key >= wk) continue;
+            bool lt[kSaoMaxN];
+#pragma unroll
+            for (int q = 0; q < kSaoMaxN; ++q) lt[q] = key < K[q];
+#pragma unroll
+            for (int q = kSaoMaxN - 1; q >= 1; --q)
+              if (lt[q]) K[q] = lt[q - 1] ? K[q - 1] : key;
+            if (lt[0]) K[0] = key;
+#pragma unroll
+            for (int q = 0; q < kSaoMaxN; ++q)
+              if (q == n - 1) wk = K[q];
+          } else {
+            if (!lex_less(d2, p.z, wd, wi)) continue;
+            near_insert(L, d2, p.z);
+#pragma unroll
+            for (int q = 0; q < kSaoMaxN; ++q)
+              if (q == n - 1) {
+                wd = L.d[q];
+                wi = L.i[q];
+              }
+          }
         }
       }
     }
     if (found >= n) {
-      uint64_t worst = 0;
-#pragma unroll
-      for (int k = 0; k < kSaoMaxN; ++k)
-        if (k == n - 1) worst = L.d[k];
-      const int64_t lb = r * g.cell;
-      if (lb > kSaoSqrtMax || (uint64_t)(lb * lb) >= worst) break;
+      // every point not yet seen lies outside the block of cells scanned so
+      // far, at least as far as the block's nearest edge inside the grid
+      const int64_t inf = INT64_MAX;
+      const int64_t dl = ix - r > 0 ? x - (g.x0 + (int64_t)(ix - r) * g.cell) : inf;
+      const int64_t dr = ix + r < nx - 1 ? g.x0 + (int64_t)(ix + r + 1) * g.cell - x : inf;
+      const int64_t dd = iy - r > 0 ? y - (g.y0 + (int64_t)(iy - r) * g.cell) : inf;
+      const int64_t du = iy + r < ny - 1 ? g.y0 + (int64_t)(iy + r + 1) * g.cell - y : inf;
+      const int64_t lb = min(min(dl, dr), min(dd, du));
+      const uint64_t worst = PACKED ? (wk >> 16) : wd;
+      if (lb > kSaoSqrtMax || (uint64_t)(lb * lb) > worst) break;  // a point at lb could still tie
     }
   }
+#pragma unroll
+  for (int k = 0; k < kSaoMaxN; ++k) out[k] = PACKED ? (int32_t)(K[k] & 0xFFFFu) : L.i[k];
 }
 
 struct Polar {
   int32_t dx, dy;
-  uint64_t d2;
   int32_t label;
 };
 
@@ -221,7 +276,10 @@ __device__ inline bool angle_less(const Polar& u, const Polar& v) {
     const int64_t cross = (int64_t)u.dx * v.dy - (int64_t)u.dy * v.dx;
     if (cross != 0) return cross > 0;
   }
-  if (u.d2 != v.d2) return u.d2 < v.d2;
+  // same direction: nearer first (the squared lengths only on this rare path)
+  const uint64_t du = (uint64_t)((int64_t)u.dx * u.dx + (int64_t)u.dy * u.dy);
+  const uint64_t dv = (uint64_t)((int64_t)v.dx * v.dx + (int64_t)v.dy * v.dy);
+  if (du != dv) return du < dv;
   return u.label < v.label;
 }
 
@@ -278,184 +336,209 @@ __device__ inline int cyclic_edit_distance(const int32_t (&a)[kSaoMaxN], int32_t
   return best;
 }
 
-__device__ inline int2 point_of(const SaoArgs& a, const SaoPair& P, const Slab& S, int side, int32_t c) {
-  const int32_t row = S.rows[c];
-  if (side == 0) return make_int2(P.kq[2 * (int64_t)row], P.kq[2 * (int64_t)row + 1]);
-  const int32_t m = a.match[P.off + row];  // validated during compaction
-  return make_int2(P.kd[2 * (int64_t)m], P.kd[2 * (int64_t)m + 1]);
+typedef int32_t v2i __attribute__((ext_vector_type(2)));
+typedef __attribute__((address_space(1))) const v2i gcv2i;
+typedef __attribute__((address_space(1))) const int32_t gci32;
+
+__device__ inline int2 ldg_xy(const int32_t* p) {
+  const v2i v = *(gcv2i*)p;
+  return make_int2(v.x, v.y);
 }
 
-__global__ __launch_bounds__(kSaoWG) void k_sao(SaoArgs a) {
-  __shared__ int s_tmp[kSaoWaves];
+// Keypoint of compact match c in image `side` (0 query, 1 db).
+__device__ inline int2 point_of(const SaoArgs& a, const SaoPair& P, const int32_t* rows, int side,
+                                int32_t c) {
+  const int32_t row = *(gci32*)(rows + c);
+  if (side == 0) return ldg_xy(P.kq + 2 * (int64_t)row);
+  const int32_t m = *(gci32*)(a.match + P.off + row);  // validated during compaction
+  return ldg_xy(P.kd + 2 * (int64_t)m);
+}
+
+__global__ __launch_bounds__(kSaoBuildWG) void k_sao_build(SaoArgs a) {
+  __shared__ int s_tmp[kSaoBuildWaves];
   __shared__ int s_M, s_bad;
-  __shared__ int s_red[4][kSaoWaves];
+  __shared__ int s_red[4][kSaoBuildWaves];
   __shared__ GridInfo s_grid;
-  const Slab S = slab_at(a.slabs + a.slab_bytes * blockIdx.x, a.n_max);
+  const int p = blockIdx.x;
+  const PairScratch S = scratch_at(a, p);
+  const SaoPair P = a.pairs[p];
   const int tid = threadIdx.x;
-
-  for (int p = blockIdx.x; p < a.n_pairs; p += gridDim.x) {
-    const SaoPair P = a.pairs[p];
-    const int nq = min(max(P.nq, 0), a.n_max);
+  const int nq = min(max(P.nq, 0), a.n_max);
+  if (tid == 0) {
+    s_M = 0;
+    s_bad = P.nq > a.n_max || P.nq < 0 ? 1 : 0;
+  }
+  phase_barrier();
+  // compaction of the matched rows in row order (and every output starts
+  // at -1): each thread counts its own segment of rows, one block scan
+  // gives the segments' starts, then each thread writes its rows
+  const int seg = (nq + kSaoBuildWG - 1) / kSaoBuildWG;
+  const int r0 = min(tid * seg, nq), r1 = min(r0 + seg, nq);
+  int mine = 0;
+  for (int i = r0; i < r1; ++i) {
+    const int32_t m = a.match[P.off + i];
+    if (m >= P.nd) s_bad = 1;
+    mine += (m >= 0 && m < P.nd) ? 1 : 0;
+  }
+  int total;
+  int pos = block_exclusive<kSaoBuildWaves>(mine, s_tmp, &total);
+  for (int i = r0; i < r1; ++i) {
+    const int32_t m = a.match[P.off + i];
+    a.out[P.off + i] = -1;
+    if (a.ced) a.ced[P.off + i] = -1;
+    if (m >= 0 && m < P.nd) S.rows[pos++] = i;
+  }
+  if (tid == 0) s_M = total;
+  phase_barrier();
+  const int M = s_M;
+  // a grid per image
+  for (int side = 0; side < 2 && M > 1; ++side) {
+    int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
+    for (int c = tid; c < M; c += kSaoBuildWG) {
+      const int2 q = point_of(a, P, S.rows, side, c);
+      if (q.x <= -kSaoCoordLimit || q.x >= kSaoCoordLimit || q.y <= -kSaoCoordLimit || q.y >= kSaoCoordLimit)
+        s_bad = 1;
+      xmin = min(xmin, q.x);
+      ymin = min(ymin, q.y);
+      xmax = max(xmax, q.x);
+      ymax = max(ymax, q.y);
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) {
+      xmin = min(xmin, __shfl_xor(xmin, d));
+      ymin = min(ymin, __shfl_xor(ymin, d));
+      xmax = max(xmax, __shfl_xor(xmax, d));
+      ymax = max(ymax, __shfl_xor(ymax, d));
+    }
+    if (__lane_id() == 0) {
+      s_red[0][tid >> 6] = xmin;
+      s_red[1][tid >> 6] = ymin;
+      s_red[2][tid >> 6] = xmax;
+      s_red[3][tid >> 6] = ymax;
+    }
+    phase_barrier();
     if (tid == 0) {
-      s_M = 0;
-      s_bad = P.nq > a.n_max || P.nq < 0 ? 1 : 0;
+      int64_t x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
+      for (int w = 0; w < kSaoBuildWaves; ++w) {
+        x0 = min(x0, (int64_t)s_red[0][w]);
+        y0 = min(y0, (int64_t)s_red[1][w]);
+        x1 = max(x1, (int64_t)s_red[2][w]);
+        y1 = max(y1, (int64_t)s_red[3][w]);
+      }
+      const double w = double(x1 - x0) + 1.0, h = double(y1 - y0) + 1.0;
+      int64_t cell = max(int64_t(1), (int64_t)ceil(sqrt(w * h * 2.0 / double(M))));
+      int64_t nx, ny;
+      for (;;) {  // at most 4 M + 64 cells, so the cell array always fits
+        nx = (x1 - x0) / cell + 1;
+        ny = (y1 - y0) / cell + 1;
+        if ((double)nx * (double)ny <= 4.0 * (double)M + 64.0) break;
+        cell *= 2;
+      }
+      s_grid = GridInfo{x0, y0, cell, nx, ny};
+      S.info->g[side] = s_grid;
     }
     phase_barrier();
-    // 1. compaction of the matched rows (and the outputs start at -1)
-    for (int base = 0; base < nq; base += kSaoWG) {
-      const int i = base + tid;
-      int32_t m = -1;
-      if (i < nq) {
-        m = a.match[P.off + i];
-        a.out[P.off + i] = -1;
-        if (a.ced) a.ced[P.off + i] = -1;
-        if (m >= P.nd) s_bad = 1;
-      }
-      const int flag = (m >= 0 && m < P.nd) ? 1 : 0;
+    const GridInfo g = s_grid;
+    const int64_t ncell = g.nx * g.ny;
+    int32_t* cell = S.cell[side];
+    for (int64_t k = tid; k <= ncell; k += kSaoBuildWG) cell[k] = 0;
+    phase_barrier();
+    for (int c = tid; c < M; c += kSaoBuildWG) {
+      const int2 q = point_of(a, P, S.rows, side, c);
+      const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
+      const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
+      atomicAdd(&cell[cy * g.nx + cx], 1);
+    }
+    phase_barrier();
+    int run = 0;  // exclusive scan: cell[k] = first slot of cell k
+    for (int64_t base = 0; base < ncell; base += kSaoBuildWG) {
+      const int64_t k = base + tid;
+      const int v = k < ncell ? cell[k] : 0;
       int total;
-      const int pos = block_exclusive(flag, s_tmp, &total);
-      if (flag) S.rows[s_M + pos] = i;
-      phase_barrier();
-      if (tid == 0) s_M += total;
-      phase_barrier();
+      const int ex = block_exclusive<kSaoBuildWaves>(v, s_tmp, &total);
+      if (k < ncell) cell[k] = run + ex;
+      run += total;
     }
-    const int M = s_M;
-    const int n = M > 0 ? min(a.nn, M - 1) : 0;
-
-    // 2. per image: grid, then the N nearest of every match
-    for (int side = 0; side < 2 && n > 0; ++side) {
-      int32_t* nbr = side ? S.nbr[1] : S.nbr[0];
-      int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
-      for (int c = tid; c < M; c += kSaoWG) {
-        const int2 q = point_of(a, P, S, side, c);
-        if (q.x <= -kSaoCoordLimit || q.x >= kSaoCoordLimit || q.y <= -kSaoCoordLimit || q.y >= kSaoCoordLimit)
-          s_bad = 1;
-        xmin = min(xmin, q.x);
-        ymin = min(ymin, q.y);
-        xmax = max(xmax, q.x);
-        ymax = max(ymax, q.y);
-      }
-#pragma unroll
-      for (int d = 32; d >= 1; d >>= 1) {
-        xmin = min(xmin, __shfl_xor(xmin, d));
-        ymin = min(ymin, __shfl_xor(ymin, d));
-        xmax = max(xmax, __shfl_xor(xmax, d));
-        ymax = max(ymax, __shfl_xor(ymax, d));
-      }
-      if (__lane_id() == 0) {
-        s_red[0][tid >> 6] = xmin;
-        s_red[1][tid >> 6] = ymin;
-        s_red[2][tid >> 6] = xmax;
-        s_red[3][tid >> 6] = ymax;
-      }
-      phase_barrier();
-      if (tid == 0) {
-        int64_t x0 = INT32_MAX, y0 = INT32_MAX, x1 = INT32_MIN, y1 = INT32_MIN;
-        for (int w = 0; w < kSaoWaves; ++w) {
-          x0 = min(x0, (int64_t)s_red[0][w]);
-          y0 = min(y0, (int64_t)s_red[1][w]);
-          x1 = max(x1, (int64_t)s_red[2][w]);
-          y1 = max(y1, (int64_t)s_red[3][w]);
-        }
-        const double w = double(x1 - x0) + 1.0, h = double(y1 - y0) + 1.0;
-        int64_t cell = max(int64_t(1), (int64_t)ceil(sqrt(w * h * 2.0 / double(M))));
-        int64_t nx, ny;
-        for (;;) {  // at most 4 M + 64 cells, so the cell array always fits
-          nx = (x1 - x0) / cell + 1;
-          ny = (y1 - y0) / cell + 1;
-          if ((double)nx * (double)ny <= 4.0 * (double)M + 64.0) break;
-          cell *= 2;
-        }
-        s_grid = GridInfo{x0, y0, cell, nx, ny};
-      }
-      phase_barrier();
-      const GridInfo g = s_grid;
-      const int64_t ncell = g.nx * g.ny;
-      for (int64_t k = tid; k <= ncell; k += kSaoWG) S.cell[k] = 0;
-      phase_barrier();
-      for (int c = tid; c < M; c += kSaoWG) {
-        const int2 q = point_of(a, P, S, side, c);
-        const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
-        const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
-        const int32_t cid = (int32_t)(cy * g.nx + cx);
-        S.cell_of[c] = cid;
-        atomicAdd(&S.cell[cid], 1);
-      }
-      phase_barrier();
-      // exclusive scan: cell[k] = first slot of cell k
-      int run = 0;
-      for (int64_t base = 0; base < ncell; base += kSaoWG) {
-        const int64_t k = base + tid;
-        const int v = k < ncell ? S.cell[k] : 0;
-        int total;
-        const int ex = block_exclusive(v, s_tmp, &total);
-        if (k < ncell) S.cell[k] = run + ex;
-        run += total;
-      }
-      phase_barrier();
-      // scatter; afterwards cell[k] is the end of cell k (= start of k + 1)
-      for (int c = tid; c < M; c += kSaoWG) {
-        const int2 q = point_of(a, P, S, side, c);
-        const int32_t slot = atomicAdd(&S.cell[S.cell_of[c]], 1);
-        S.pts[min(max(slot, 0), M - 1)] = make_int4(q.x, q.y, c, 0);
-      }
-      phase_barrier();
-      for (int c = tid; c < M; c += kSaoWG) {
-        const int2 q = point_of(a, P, S, side, c);
-        NearList L;
-        ring_search(S, g, q.x, q.y, c, n, L);
-#pragma unroll
-        for (int k = 0; k < kSaoMaxN; ++k)
-          if (k < n) nbr[(int64_t)c * kSaoMaxN + k] = min(max(L.i[k], 0), M - 1);
-      }
-      phase_barrier();
-    }
-
-    // 3. angular orders, cyclic edit distance, verdict
-    const bool bad = s_bad != 0;
-    for (int c = tid; c < M && !bad; c += kSaoWG) {
-      const int32_t row = S.rows[c];
-      const int32_t m = a.match[P.off + row];
-      int dist = 0;
-      if (n > 0) {
-        int32_t lab[2][kSaoMaxN];
-#pragma unroll
-        for (int side = 0; side < 2; ++side) {
-          const int2 o = point_of(a, P, S, side, c);
-          Polar e[kSaoMaxN];
-#pragma unroll
-          for (int k = 0; k < kSaoMaxN; ++k) {
-            const int32_t nb = k < n ? (side ? S.nbr[1] : S.nbr[0])[(int64_t)c * kSaoMaxN + k] : c;
-            const int2 q = point_of(a, P, S, side, nb);
-            const int32_t dx = q.x - o.x, dy = q.y - o.y;
-            e[k] = Polar{dx, dy, (uint64_t)((int64_t)dx * dx + (int64_t)dy * dy), nb};
-          }
-          sort_by_angle(e, n);
-#pragma unroll
-          for (int k = 0; k < kSaoMaxN; ++k) lab[side][k] = e[k].label;
-        }
-        dist = cyclic_edit_distance(lab[0], lab[1], n);
-      }
-      if ((int64_t)dist * a.den <= (int64_t)a.num * n) a.out[P.off + row] = m;
-      if (a.ced) a.ced[P.off + row] = dist;
-    }
-    if (tid == 0 && bad) atomicAdd(a.errors, 1);
     phase_barrier();
+    // scatter; afterwards cell[k] is the end of cell k (the start of k + 1)
+    int4* pts = S.pts[side];
+    for (int c = tid; c < M; c += kSaoBuildWG) {
+      const int2 q = point_of(a, P, S.rows, side, c);
+      const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
+      const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
+      const int32_t slot = atomicAdd(&cell[cy * g.nx + cx], 1);
+      pts[min(max(slot, 0), M - 1)] = make_int4(q.x, q.y, c, 0);
+    }
+    phase_barrier();
+  }
+  if (tid == 0) {
+    S.info->M = M;
+    S.info->bad = s_bad;
+    if (s_bad) atomicAdd(a.errors, 1);
+  }
+}
+
+__global__ __launch_bounds__(kSaoWG) void k_sao_search(SaoArgs a) {
+  const int p = blockIdx.y;
+  const PairScratch S = scratch_at(a, p);
+  const int M = S.info->M;
+  if ((int)(blockIdx.x * kSaoWG) >= M || S.info->bad) return;  // uniform over the work-group
+  // threads take the matches in the query image's cell order, so the lanes
+  // of a wavefront search neighbouring cells (one match: no grid, row order)
+  const int32_t t = (int32_t)(blockIdx.x * kSaoWG + threadIdx.x);
+  const bool active = t < M;
+  const int32_t c = !active ? 0 : M > 1 ? min(max(S.pts[0][t].z, 0), M - 1) : t;
+  const SaoPair P = a.pairs[p];
+  const int n = min(a.nn, M - 1);
+  int dist = 0;
+  if (n > 0) {
+    int32_t lab[2][kSaoMaxN];
+#pragma unroll
+    for (int side = 0; side < 2; ++side) {
+      const GridInfo g = S.info->g[side];
+      if (active) {
+        const int2 o = point_of(a, P, S.rows, side, c);
+        int32_t nn_idx[kSaoMaxN];
+        const GlobalGrid G{S.cell[side], S.pts[side]};
+        // packed keys when every coordinate difference is below 2^23
+        if (g.nx * g.cell < (int64_t(1) << 23) && g.ny * g.cell < (int64_t(1) << 23) && M <= 65536)
+          ring_search<true>(G, g, o.x, o.y, c, n, nn_idx);
+        else
+          ring_search<false>(G, g, o.x, o.y, c, n, nn_idx);
+        Polar e[kSaoMaxN];
+#pragma unroll
+        for (int k = 0; k < kSaoMaxN; ++k) {
+          const int32_t nb = k < n ? min(max(nn_idx[k], 0), M - 1) : c;
+          const int2 q = point_of(a, P, S.rows, side, nb);
+          e[k] = Polar{q.x - o.x, q.y - o.y, nb};
+        }
+        sort_by_angle(e, n);
+#pragma unroll
+        for (int k = 0; k < kSaoMaxN; ++k) lab[side][k] = e[k].label;
+      }
+    }
+    if (active) dist = cyclic_edit_distance(lab[0], lab[1], n);
+  }
+  if (active) {
+    const int32_t row = S.rows[c];
+    const int32_t m = a.match[P.off + row];
+    if ((int64_t)dist * a.den <= (int64_t)a.num * n) a.out[P.off + row] = m;
+    if (a.ced) a.ced[P.off + row] = dist;
   }
 }
 
 }  // namespace
 
 static uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows) {
-  const int64_t G = std::min<int64_t>(std::max(n_pairs, 1), kSaoGrid);
+  const int64_t B = std::min<int64_t>(std::max(n_pairs, 1), kSaoBatch);
   return 256 + round16(sizeof(SaoPair) * (uint64_t)std::max(n_pairs, 1)) +
-         (uint64_t)G * slab_bytes(std::max(max_rows, 1));
+         (uint64_t)B * pair_scratch_bytes(std::max(max_rows, 1));
 }
 
 static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
-                      const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match,
-                      int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
-                      hipStream_t s) {
+                             const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match,
+                             int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
+                             hipStream_t s) {
   int32_t n_max = 1;
   std::vector<SaoPair> hp((size_t)n_pairs);
   for (int32_t p = 0; p < n_pairs; ++p) {
@@ -470,8 +553,6 @@ static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int3
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // hp is freed on return
   if (e != hipSuccess) return e;
   SaoArgs a;
-  a.pairs = dp;
-  a.n_pairs = n_pairs;
   a.n_max = n_max;
   a.match = d_match;
   a.out = d_out;
@@ -479,12 +560,19 @@ static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int3
   a.nn = nn;
   a.num = num;
   a.den = den;
-  a.slabs = w + 256 + round16(sizeof(SaoPair) * (uint64_t)n_pairs);
-  a.slab_bytes = slab_bytes(n_max);
+  a.scratch = w + 256 + round16(sizeof(SaoPair) * (uint64_t)n_pairs);
+  a.scratch_bytes = pair_scratch_bytes(n_max);
   a.errors = reinterpret_cast<int32_t*>(w);
-  const int grid = std::min(n_pairs, kSaoGrid);
-  hipLaunchKernelGGL(k_sao, dim3(grid), dim3(kSaoWG), 0, s, a);
-  return hipGetLastError();
+  const unsigned chunks = (unsigned)((n_max + kSaoWG - 1) / kSaoWG);
+  for (int32_t b0 = 0; b0 < n_pairs; b0 += kSaoBatch) {
+    a.pairs = dp + b0;
+    a.n_pairs = std::min(kSaoBatch, n_pairs - b0);
+    hipLaunchKernelGGL(k_sao_build, dim3(a.n_pairs), dim3(kSaoBuildWG), 0, s, a);
+    hipLaunchKernelGGL(k_sao_search, dim3(chunks, a.n_pairs), dim3(kSaoWG), 0, s, a);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
 }
 
 }  // namespace chm
