@@ -51,6 +51,8 @@ def parse():
     ap.add_argument("--caps", default="16,2", help="grid workload: residency caps in GB")
     ap.add_argument("--size-blk", type=int, default=400, help="grid workload: Size_blk (images)")
     ap.add_argument("--grid-shape", default="50,100,10000", help="grid workload: rows,cols,features")
+    ap.add_argument("--grid-sao", action="store_true",
+                    help="grid workload: also run the first cap with the device SAO filter per step")
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-reuse", action="store_true",
                     help="also time the plain path re-hashing both images of every pair")
@@ -400,6 +402,25 @@ def run_grid(args):
                      "iterations": sched.iterations, "fallback_pairs": sched.fallback_pairs,
                      "mbr_dims": sched.dims, "schedule_seconds": round(t_sched, 3)})
         say("cap %.0f GB: %.3f s, %.0f pairs/s, %.2f GB H2D" % (cap_gb, wall, P / wall, st.h2d_bytes / 1e9))
+        if args.grid_sao and cap_gb == float(args.caps.split(",")[0]):
+            # the same schedule again, with the device SAO filter after each step
+            store.close()
+            store = chm.Store(cfg, wl.W, wl.mu, arena)
+            kps = synth.keypoints(wl)
+            d_kps = [torch.from_numpy(k).to(dev) for k in kps]
+            filt = torch.empty_like(out)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            work = chm.run_schedule_sao(store, sched, wl.pairs, views, offs, out, d_kps, filt)
+            torch.cuda.synchronize()
+            wall_s = time.perf_counter() - t0
+            f = filt.cpu().numpy()
+            m = out.cpu().numpy()
+            runs[-1]["with_device_sao"] = {"seconds": round(wall_s, 4), "pairs_per_s": round(P / wall_s, 1),
+                                           "matches": int((m >= 0).sum()), "kept": int((f >= 0).sum()),
+                                           "input_errors": chm.sao_input_errors(work)}
+            say("cap %.0f GB with SAO: %.3f s, %.0f pairs/s" % (cap_gb, wall_s, P / wall_s))
+            del d_kps, work, filt
         chm.schedule_free(sched)
         store.close()
         del arena

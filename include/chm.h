@@ -359,6 +359,21 @@ chm_status chm_sao_filter_device(int32_t n_pairs, const int32_t *h_pairs, const 
                                  int32_t score_den, int32_t *d_out, int32_t *d_ced, void *d_work,
                                  uint64_t work_bytes, void *stream);
 
+/* chm_run_schedule with outlier removal beside the block rows (Algorithm 1):
+ * after each step's batched matching, the device SAO filter of that step's
+ * pairs runs on the same stream and writes d_filtered (laid out like d_out).
+ *   n_images   : entries of h_descs, h_n_feats and d_kp.
+ *   d_kp, n_neighbors, score_num, score_den : as in chm_sao_filter_device.
+ *   d_work     : 256-byte aligned, chm_sao_work_bytes(n_pairs, largest
+ *                query image) bytes; its first int32 counts, over the whole
+ *                run, the pairs whose SAO input broke the contract. */
+chm_status chm_run_schedule_sao(chm_store *store, const chm_schedule *s, const int32_t *h_pairs,
+                                int32_t n_pairs, const void *const *h_descs, const int32_t *h_n_feats,
+                                int32_t n_images, const int64_t *h_out_offsets, int32_t *d_out,
+                                const int32_t *const *d_kp, int32_t n_neighbors, int32_t score_num,
+                                int32_t score_den, int32_t *d_filtered, void *d_work,
+                                uint64_t work_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

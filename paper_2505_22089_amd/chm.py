@@ -62,6 +62,7 @@ EXPORTS = [
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
+    "chm_run_schedule_sao",
 ]
 
 _lib = None
@@ -107,6 +108,8 @@ def lib():
             "chm_sao_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, i32, vp, vp]),
             "chm_sao_work_bytes": (i32, [i32, i32, P(u64)]),
             "chm_sao_filter_device": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, u64, vp]),
+            "chm_run_schedule_sao": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, u64,
+                                           vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -396,6 +399,31 @@ def run_schedule(store: Store, sched: Schedule, pairs: np.ndarray, descs: Sequen
     offs = np.ascontiguousarray(offs, dtype=np.int64)
     _check(lib().chm_run_schedule(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
                                   _np_ptr(ns), _np_ptr(offs), _dev_ptr(out), _stream(stream)))
+
+
+def run_schedule_sao(store: Store, sched: Schedule, pairs: np.ndarray, descs: Sequence[np.ndarray],
+                     offs: np.ndarray, out, keypoints, filtered, work=None, n_neighbors: int = 6,
+                     threshold=(1, 2), stream=None):
+    """run_schedule plus the device SAO filter of every step's pairs
+    (keypoints: device (n, 2) int32 tensors per image).  Returns the work
+    tensor (see sao_input_errors)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    keep = [np.ascontiguousarray(d, dtype=np.uint8) for d in descs]
+    parr = (C.c_void_p * len(keep))(*[k.ctypes.data for k in keep])
+    ns = np.ascontiguousarray([k.shape[0] for k in keep], dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    kptr = (C.c_void_p * len(keypoints))(*[_dev_ptr(k) for k in keypoints])
+    if work is None:
+        import torch
+        nmax = int(max((ns[q] for q in pairs[:, 0]), default=1))
+        work = torch.empty(sao_work_bytes(len(pairs), nmax) + 256, dtype=torch.uint8, device=out.device)
+        work = work[(-work.data_ptr()) % 256:]
+    _check(lib().chm_run_schedule_sao(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
+                                      _np_ptr(ns), len(keep), _np_ptr(offs), _dev_ptr(out),
+                                      C.cast(kptr, C.c_void_p), n_neighbors, int(threshold[0]),
+                                      int(threshold[1]), _dev_ptr(filtered), _dev_ptr(work),
+                                      int(work.numel()), _stream(stream)))
+    return work
 
 
 def sao_filter(keypoints: Sequence[np.ndarray], pairs: np.ndarray, offs: np.ndarray,

@@ -64,6 +64,16 @@ struct MatchArgs {
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
 };
 
+// Device SAO (sao_device.hip).  h_starts[p] is where pair p's query rows
+// begin in d_match / d_out / d_ced (only starts are read); the caller has
+// checked the arguments.  clear_errors zeroes the work buffer's error word.
+constexpr int kSaoMaxNeighbors = 8;
+uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows);
+hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_starts, const int32_t* d_match, int32_t nn,
+                      int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work, bool clear_errors,
+                      hipStream_t s);
+
 // Items of at most kSortMax queries are processed in order of walk length.
 // LDS after the staged codes and offsets: two control words (16 B), the
 // sort's histogram (256 u32), order (u16) and lengths (u8).

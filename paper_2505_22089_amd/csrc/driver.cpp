@@ -1,9 +1,12 @@
 // End-to-end run of an MBR schedule (Algorithm 1, CascadeHashingMatching):
 // per block row, free what the row no longer needs, load the new images
 // (descriptors host -> HBM, then codes and tables on the device) and match
-// the row's pairs in one batched launch.
+// the row's pairs in one batched launch; optionally the row's matches then
+// go through the SAO local constraint on the device (Sec. 2.3.3), on the
+// same stream, so outlier removal keeps pace with the block rows.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "chm.h"
@@ -12,10 +15,18 @@
 
 using namespace chm;
 
-extern "C" chm_status chm_run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
-                                       int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
-                                       const int64_t* h_offs, int32_t* d_out, void* stream) {
-  clear_error();
+namespace {
+
+struct SaoStep {
+  const int32_t* const* d_kp;
+  int32_t nn, num, den;
+  int32_t* d_filtered;
+  void* d_work;
+};
+
+chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P,
+                        const void* const* h_descs, const int32_t* h_n_feats, const int64_t* h_offs,
+                        int32_t* d_out, void* stream, const SaoStep* sao) {
   if (!S || !sc) return fail(CHM_E_INVALID_ARG, "NULL argument");
   if (P < 0 || (P && (!h_pairs || !h_offs)) || !h_descs || !h_n_feats)
     return fail(CHM_E_INVALID_ARG, "bad arguments");
@@ -55,10 +66,54 @@ extern "C" chm_status chm_run_schedule(chm_store* S, const chm_schedule* sc, con
     st = chm_plan_execute(pl, stream);
     chm_plan_destroy(pl);
     if (st) return st;
+    if (sao && npp > 0) {
+      const hipError_t e = launch_sao(npp, sp.data(), sao->d_kp, h_n_feats, starts.data(), d_out, sao->nn,
+                                      sao->num, sao->den, sao->d_filtered, nullptr, sao->d_work, false,
+                                      (hipStream_t)stream);
+      if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
+    }
   }
   hipError_t e = hipStreamSynchronize((hipStream_t)stream);
   if (e != hipSuccess) return fail(CHM_E_HIP, "schedule run failed: %s", hipGetErrorString(e));
   return CHM_OK;
+}
+
+}  // namespace
+
+extern "C" chm_status chm_run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
+                                       int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
+                                       const int64_t* h_offs, int32_t* d_out, void* stream) {
+  clear_error();
+  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, nullptr);
+}
+
+extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
+                                           int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
+                                           int32_t n_images, const int64_t* h_offs, int32_t* d_out,
+                                           const int32_t* const* d_kp, int32_t n_neighbors, int32_t score_num,
+                                           int32_t score_den, int32_t* d_filtered, void* d_work,
+                                           uint64_t work_bytes, void* stream) {
+  clear_error();
+  if (!d_kp || !h_n_feats || !d_filtered || !d_work || d_filtered == d_out)
+    return fail(CHM_E_INVALID_ARG, "bad SAO buffers");
+  if (n_neighbors < 1 || n_neighbors > kSaoMaxNeighbors)
+    return fail(CHM_E_INVALID_ARG, "n_neighbors must be 1..%d on the device", kSaoMaxNeighbors);
+  if (score_num < 0 || score_den <= 0) return fail(CHM_E_INVALID_ARG, "bad score threshold");
+  if (reinterpret_cast<uintptr_t>(d_work) % 256) return fail(CHM_E_INVALID_ARG, "d_work must be 256-byte aligned");
+  int32_t n_max = 0;
+  for (int32_t p = 0; p < P; ++p) {
+    const int32_t q = h_pairs ? h_pairs[2 * p] : -1, d = h_pairs ? h_pairs[2 * p + 1] : -1;
+    if (q < 0 || q >= n_images || d < 0 || d >= n_images)
+      return fail(CHM_E_INVALID_ARG, "pair %d names an image outside 0..%d", p, n_images - 1);
+    if ((h_n_feats[q] > 0 && !d_kp[q]) || (h_n_feats[d] > 0 && !d_kp[d]))
+      return fail(CHM_E_INVALID_ARG, "pair %d: NULL keypoints", p);
+    n_max = std::max(n_max, h_n_feats[q]);
+  }
+  if (work_bytes < sao_work_bytes(P, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
+  const hipError_t e = launch_fill_u32(static_cast<uint32_t*>(d_work), 0u, 1, (hipStream_t)stream);
+  if (e != hipSuccess) return fail(CHM_E_HIP, "%s", hipGetErrorString(e));
+  const SaoStep sao{d_kp, n_neighbors, score_num, score_den, d_filtered, d_work};
+  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao);
 }
 
 extern "C" chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t* out) {

@@ -34,7 +34,7 @@ namespace {
 constexpr int kSaoWG = 256;                        // search: one thread per match
 constexpr int kSaoBuildWG = 256;                   // build: one work-group per pair
 constexpr int kSaoBuildWaves = kSaoBuildWG / 64;
-constexpr int kSaoMaxN = 8;
+constexpr int kSaoMaxN = kSaoMaxNeighbors;
 constexpr int kSaoBatch = 512;  // pairs per launch pair (scratch is per pair)
 constexpr int64_t kSaoCoordLimit = int64_t(1) << 30;
 constexpr int64_t kSaoSqrtMax = 3037000499LL;  // floor(sqrt(2^63 - 1))
@@ -529,16 +529,16 @@ __global__ __launch_bounds__(kSaoWG) void k_sao_search(SaoArgs a) {
 
 }  // namespace
 
-static uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows) {
+uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows) {
   const int64_t B = std::min<int64_t>(std::max(n_pairs, 1), kSaoBatch);
   return 256 + round16(sizeof(SaoPair) * (uint64_t)std::max(n_pairs, 1)) +
          (uint64_t)B * pair_scratch_bytes(std::max(max_rows, 1));
 }
 
-static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
-                             const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match,
-                             int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
-                             hipStream_t s) {
+hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match, int32_t nn,
+                      int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work, bool clear_errors,
+                      hipStream_t s) {
   int32_t n_max = 1;
   std::vector<SaoPair> hp((size_t)n_pairs);
   for (int32_t p = 0; p < n_pairs; ++p) {
@@ -548,7 +548,7 @@ static hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int3
   }
   uint8_t* w = static_cast<uint8_t*>(d_work);
   SaoPair* dp = reinterpret_cast<SaoPair*>(w + 256);
-  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, 1, s);
+  hipError_t e = clear_errors ? launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, 1, s) : hipSuccess;
   if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), sizeof(SaoPair) * hp.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess) e = hipStreamSynchronize(s);  // hp is freed on return
   if (e != hipSuccess) return e;
@@ -618,7 +618,7 @@ extern "C" chm_status chm_sao_filter_device(int32_t n_pairs, const int32_t* h_pa
     return fail(CHM_E_CAPACITY, "work buffer holds %llu bytes, %llu needed", (unsigned long long)work_bytes,
                 (unsigned long long)need);
   const hipError_t e = launch_sao(n_pairs, h_pairs, d_kp, h_n_feats, h_offs, d_match, n_neighbors, score_num,
-                                  score_den, d_out, d_ced, d_work, (hipStream_t)stream);
+                                  score_den, d_out, d_ced, d_work, true, (hipStream_t)stream);
   if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
   return CHM_OK;
 }

@@ -136,3 +136,35 @@ def test_device_sao_on_matcher_output_with_repeated_texture():
         assert np.array_equal(g_ced[offs[p] + rows], rc[rows])
         assert np.array_equal(g_out[offs[p] + rows], rf[rows])
     assert (g_ced[out < 0] == -1).all() and (g_out[out < 0] == -1).all()
+
+
+def test_schedule_with_sao_per_block_row():
+    """An MBR schedule under a binding cap with the SAO filter after every
+    step: the matches equal the plain schedule run (and the oracle), the
+    filtered matches equal the host SAO of those matches."""
+    from oracle import oracle as O
+    from tests.gpu_helpers import device
+    wl = synth.config5(rows=6, cols=20, n_feats=1500)
+    kps = synth.keypoints(wl)
+    n = len(wl.images)
+    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio)
+    sizes = [chm.image_bytes(cfg, x.shape[0]) + 256 for x in wl.images]
+    cap = 30 * sizes[0]
+    sched = chm.schedule_mbr(n, wl.pairs, sizes, cap, 12, keep_handle=True)
+    assert len(sched.steps) > 1
+    arena = torch.empty(chm.store_overhead_bytes(cfg) + cap + (16 << 20), dtype=torch.uint8, device=device())
+    st = chm.Store(cfg, wl.W, wl.mu, arena)
+    offs = np.zeros(len(wl.pairs) + 1, np.int64)
+    offs[1:] = np.cumsum([wl.images[q].shape[0] for q in wl.pairs[:, 0]])
+    out = torch.full((int(offs[-1]),), -7, dtype=torch.int32, device=device())
+    filt = torch.full_like(out, -7)
+    work = chm.run_schedule_sao(st, sched, wl.pairs, wl.images, offs, out, [_dev(k) for k in kps], filt)
+    torch.cuda.synchronize()
+    assert chm.sao_input_errors(work) == 0
+    chm.schedule_free(sched)
+    st.close()
+    o = out.cpu().numpy()
+    H = O.hash_workload(wl)
+    ref, _, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
+    assert np.array_equal(o, ref)
+    assert np.array_equal(filt.cpu().numpy(), chm.sao_filter(kps, wl.pairs, offs, o, 6, (1, 2)))
