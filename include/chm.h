@@ -374,6 +374,30 @@ chm_status chm_run_schedule_sao(chm_store *store, const chm_schedule *s, const i
                                 int32_t score_den, int32_t *d_filtered, void *d_work,
                                 uint64_t work_bytes, void *stream);
 
+/* RANSAC global verification (Sec. 2.3.3) of each pair's matches on host
+ * threads, with a 2D similarity as the two-view model (q = z (p - p_i) + q_i
+ * in complex notation, fixed by two matches).  Host memory only.
+ *   h_pairs, h_kp, h_n_feats, n_images, h_offs, h_match : as in
+ *                  chm_sao_filter; coordinates must satisfy |x|, |y| < 2^19.
+ *   h_words      : n_pairs x iterations x 2 random 32-bit words (the
+ *                  caller's generator): hypothesis t of pair p takes match
+ *                  i = u mod M and j = v mod (M - 1) (+1 when j >= i) of its
+ *                  M matches, in query-row order.
+ *   thr          : inlier distance in coordinate units, 0..2^20-1; match k
+ *                  is an inlier when |q_k - z (p_k - p_i) - q_i| <= thr,
+ *                  tested exactly in integers.
+ *   min_inliers  : the best hypothesis (most inliers, the earlier on ties)
+ *                  verifies the pair only with at least this many.
+ *   h_out        : verified matches (the best hypothesis' inliers), -1
+ *                  otherwise; may be h_match itself.
+ *   h_best_counts: optional, inlier count of each pair's best hypothesis.
+ * A pair with fewer than two matches verifies nothing. */
+chm_status chm_ransac_filter(int32_t n_pairs, const int32_t *h_pairs, const int32_t *const *h_kp,
+                             const int32_t *h_n_feats, int32_t n_images, const int64_t *h_offs,
+                             const int32_t *h_match, const uint32_t *h_words, int32_t iterations,
+                             int32_t thr, int32_t min_inliers, int32_t n_threads, int32_t *h_out,
+                             int32_t *h_best_counts);
+
 #ifdef __cplusplus
 }
 #endif

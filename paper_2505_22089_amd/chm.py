@@ -62,7 +62,7 @@ EXPORTS = [
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
-    "chm_run_schedule_sao",
+    "chm_run_schedule_sao", "chm_ransac_filter",
 ]
 
 _lib = None
@@ -110,6 +110,7 @@ def lib():
             "chm_sao_filter_device": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, u64, vp]),
             "chm_run_schedule_sao": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, u64,
                                            vp]),
+            "chm_ransac_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -482,3 +483,23 @@ def sao_input_errors(work) -> int:
     """Pairs of the last device SAO call on `work` whose input broke the
     contract (waits for the call)."""
     return int(work[:4].view(dtype=__import__("torch").int32).item())
+
+
+def ransac_filter(keypoints: Sequence[np.ndarray], pairs: np.ndarray, offs: np.ndarray, matches: np.ndarray,
+                  words: np.ndarray, thr: int, min_inliers: int = 8, n_threads: int = 0):
+    """RANSAC verification (Sec. 2.3.3) on host threads: (verified matches,
+    best inlier count per pair).  words: (n_pairs, iterations, 2) uint32."""
+    kps = [np.ascontiguousarray(k, dtype=np.int32) for k in keypoints]
+    nf = np.array([k.shape[0] for k in kps], dtype=np.int32)
+    ptrs = (C.c_void_p * max(1, len(kps)))(*[k.ctypes.data for k in kps])
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    matches = np.ascontiguousarray(matches, dtype=np.int32)
+    words = np.ascontiguousarray(words, dtype=np.uint32).reshape(len(pairs), -1, 2)
+    out = np.empty_like(matches)
+    best = np.empty(len(pairs), dtype=np.int32)
+    _check(lib().chm_ransac_filter(len(pairs), _np_ptr(pairs), C.cast(ptrs, C.c_void_p), _np_ptr(nf),
+                                   len(kps), _np_ptr(offs), _np_ptr(matches), _np_ptr(words),
+                                   int(words.shape[1]), int(thr), int(min_inliers), n_threads,
+                                   _np_ptr(out), _np_ptr(best)))
+    return out, best

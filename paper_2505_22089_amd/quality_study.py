@@ -10,7 +10,8 @@ same track.  Recall counts the query descriptors whose track the db image
 observes.  With --repeat-frac the workload has repeated texture (that
 fraction of the tracks look like other tracks elsewhere), which makes false
 matches that pass the ratio test; each row then also scores the matches kept
-by the SAO local constraint (Sec. 2.3.3) at a few dissimilarity thresholds.
+by the SAO local constraint (Sec. 2.3.3) at a few dissimilarity thresholds,
+and by RANSAC verification (alone and after SAO).
 Run on a GPU: python -m paper_2505_22089_amd.quality_study [--repeat-frac 0.3]
 """
 from __future__ import annotations
@@ -22,6 +23,10 @@ from typing import Dict, List, Tuple
 import numpy as np
 
 from . import chm, synth
+
+
+# RANSAC settings: 64 hypotheses, 4 px (keypoints are in 1/16 px), 8 inliers
+RANSAC_ITERS, RANSAC_THR, RANSAC_MIN = 64, 64, 8
 
 
 def _score(wl, pairs: np.ndarray, offs: np.ndarray, out: np.ndarray,
@@ -47,6 +52,7 @@ def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, 
     import torch
     wl = synth.config2(repeat_frac=repeat_frac)
     kps = synth.keypoints(wl)
+    words = synth.ransac_words(len(wl.pairs), RANSAC_ITERS)
     pairs = wl.pairs
     index = {(int(q), int(d)): p for p, (q, d) in enumerate(pairs)}
     rev = np.array([index.get((int(d), int(q)), -1) for q, d in pairs])
@@ -83,6 +89,11 @@ def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, 
             for th in sao_thresholds:
                 f = chm.sao_filter(kps, pairs, offs, out, 6, th)
                 row["sao %d/%d" % th] = _score(wl, pairs, offs, f)
+                if th == (1, 2):  # global verification after the local constraint
+                    v, _ = chm.ransac_filter(kps, pairs, offs, f, words, RANSAC_THR, RANSAC_MIN)
+                    row["sao 1/2 + ransac"] = _score(wl, pairs, offs, v)
+            v, _ = chm.ransac_filter(kps, pairs, offs, out, words, RANSAC_THR, RANSAC_MIN)
+            row["ransac"] = _score(wl, pairs, offs, v)
             rows.append(row)
             print(json.dumps(row), flush=True)
     return rows

@@ -278,6 +278,13 @@ def keypoints(wl: Workload, size_px: float = 4000.0, sigma_px: float = 1.0, subp
     return out
 
 
+def ransac_words(n_pairs: int, iterations: int, seed: int = 99) -> np.ndarray:
+    """Random 32-bit words for RANSAC hypotheses: (n_pairs, iterations, 2)
+    uint32, two per hypothesis (they pick its two matches)."""
+    rng = np.random.default_rng(seed)
+    return rng.integers(0, 1 << 32, size=(n_pairs, iterations, 2), dtype=np.uint64).astype(np.uint32)
+
+
 # ---------------------------------------------------------------- the five workloads
 
 def config1(n: int = 2000, planted: int = 1000, seed: int = 1001) -> Workload:
