@@ -315,12 +315,19 @@ def sao_leg(wl, out_b, offs, stream, reps=10, n_neighbors=6, threshold=(1, 2), h
     t0 = time.perf_counter()
     h = chm.sao_filter(kps, wl.pairs[:P], offs[:P + 1], m[:end], n_neighbors, threshold, n_threads=threads)
     host_s = time.perf_counter() - t0
+    # RANSAC verification of the SAO output on host threads (64 hypotheses, 4 px)
+    words = synth.ransac_words(P, 64)
+    t0 = time.perf_counter()
+    v, _ = chm.ransac_filter(kps, wl.pairs[:P], offs[:P + 1], g[:end], words, 64, 8, n_threads=threads)
+    ransac_s = time.perf_counter() - t0
     return {"n_neighbors": n_neighbors, "threshold": "%d/%d" % threshold,
             "device_ms": round(dev_ms, 4), "device_pairs_per_s": round(len(wl.pairs) / (dev_ms * 1e-3), 1),
             "matches_in": int((m >= 0).sum()), "kept": int((g >= 0).sum()), "input_errors": bad,
             "host_pairs": P, "host_threads": threads, "host_ms": round(host_s * 1e3, 1),
             "host_pairs_per_s": round(P / host_s, 1),
-            "device_equals_host": bool(np.array_equal(g[:end], h))}
+            "device_equals_host": bool(np.array_equal(g[:end], h)),
+            "ransac_host_ms": round(ransac_s * 1e3, 1), "ransac_host_pairs_per_s": round(P / ransac_s, 1),
+            "ransac_verified": int((v >= 0).sum())}
 
 
 def bruteforce_leg(wl, descs, stream, reps=5):
