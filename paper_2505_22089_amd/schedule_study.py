@@ -7,6 +7,10 @@ graph, for three ways of walking the pairs:
   after it (no residency at all);
 * sequential: pairs in list order, images kept resident until the cap
   forces the least recently used one out (a load/free list);
+* graph partition: the images, in GPS order, are cut into parts of at most
+  half the cap; part A is loaded once for its internal pairs, then every
+  part B that shares pairs with A is streamed through the other half (the
+  part-pair schedule of graph-partition methods);
 * MBR: the block schedule of Sec. 2.2 / Algorithm 1 (GPS order, segments of
   Size_blk images, block rows), computed by the library's scheduler.
 
@@ -53,6 +57,48 @@ def sequential_lru(pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Seq
     return {"h2d_bytes": loaded_bytes, "loads": loads, "resident_peak": peak}
 
 
+def graph_partition(n: int, pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Sequence[int],
+                    cap: int) -> Dict[str, object]:
+    """Part-pair schedule over GPS-ordered parts of at most cap / 2 bytes.
+    Returns traffic and checks: every pair once, residency within cap."""
+    edges = np.unique(np.sort(np.asarray(pairs, dtype=np.int32).reshape(-1, 2), axis=1), axis=0)
+    order = chm.gps_order(n, edges, list(range(n)))
+    part_of = np.empty(n, np.int64)
+    parts: List[List[int]] = [[]]
+    used = 0
+    for v in order:
+        if parts[-1] and used + slot_bytes[v] > cap // 2:
+            parts.append([])
+            used = 0
+        parts[-1].append(int(v))
+        part_of[v] = len(parts) - 1
+        used += slot_bytes[v]
+    by_parts: Dict[tuple, List[int]] = {}
+    for p, (q, d) in enumerate(np.asarray(pairs).reshape(-1, 2)):
+        a, b = sorted((int(part_of[q]), int(part_of[d])))
+        by_parts.setdefault((a, b), []).append(p)
+    loaded = loads = peak = 0
+    done = np.zeros(len(pairs), np.int64)
+    for a in range(len(parts)):
+        partners = sorted(b for (x, b) in by_parts if x == a and b != a)
+        if (a, a) not in by_parts and not partners:
+            continue
+        bytes_a = sum(slot_bytes[v] for v in parts[a])
+        loaded += sum(desc_bytes[v] for v in parts[a])
+        loads += len(parts[a])
+        peak = max(peak, bytes_a)
+        for p in by_parts.get((a, a), []):
+            done[p] += 1
+        for b in partners:
+            loaded += sum(desc_bytes[v] for v in parts[b])
+            loads += len(parts[b])
+            peak = max(peak, bytes_a + sum(slot_bytes[v] for v in parts[b]))
+            for p in by_parts[(a, b)]:
+                done[p] += 1
+    return {"h2d_bytes": int(loaded), "loads": int(loads), "parts": len(parts), "resident_peak": int(peak),
+            "every_pair_once": bool((done == 1).all())}
+
+
 def mbr(n: int, pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Sequence[int], cap: int,
         blk: int) -> Dict[str, object]:
     s = chm.schedule_mbr(n, pairs, slot_bytes, cap, blk)
@@ -78,7 +124,8 @@ def study(name: str, n: int, pairs: np.ndarray, feats: np.ndarray, caps_gb: List
         cap = int(cap_gb * (1 << 30))
         row = {"workload": name, "cap_GB": cap_gb, "images": n, "pairs": int(len(pairs)),
                "floor_bytes": floor, "naive_bytes": naive_bytes(pairs, desc),
-               "sequential": sequential_lru(pairs, slot, desc, cap), "mbr": {}}
+               "sequential": sequential_lru(pairs, slot, desc, cap),
+               "graph_partition": graph_partition(n, pairs, slot, desc, cap), "mbr": {}}
         for blk in blks:
             row["mbr"][blk] = mbr(n, pairs, slot, desc, cap, blk)
         out.append(row)

@@ -59,3 +59,18 @@ def test_quality_scoring_counts_planted_tracks():
     keep = [np.array([True, False, False, True])]
     r = Q._score(W, pairs, offs, out, keep)
     assert r == {"matches": 1, "precision": 1.0, "recall": 1 / 2}
+
+
+def test_graph_partition_covers_every_pair_once_within_the_cap():
+    rng = np.random.default_rng(1)
+    pairs = np.concatenate([synth.band_grid_pairs(6, 12, 1, 3), synth.cross_links(rng, 6, 12)])
+    n = 72
+    slot = [10] * n
+    desc = [8] * n
+    for cap in (200, 120, 60):
+        r = S.graph_partition(n, pairs, slot, desc, cap)
+        assert r["every_pair_once"] and r["resident_peak"] <= cap
+        assert n * 8 <= r["h2d_bytes"] <= S.naive_bytes(pairs, desc)
+    # everything fits in one part: each image is loaded once
+    r = S.graph_partition(n, pairs, slot, desc, 2 * n * 10)
+    assert r["parts"] == 1 and r["h2d_bytes"] == n * 8
