@@ -63,7 +63,7 @@ typedef struct chm_config {
   int32_t ratio_num;      /* t_r = ratio_num / ratio_den, 0 < num <= den <= 46340 */
   int32_t ratio_den;
   int32_t proj_precision; /* CHM_PROJ_BF16 or CHM_PROJ_FP32 (MFMA input type) */
-  int32_t flags;          /* CHM_ACCEPT_SINGLE or 0 */
+  int32_t flags;          /* CHM_ACCEPT_SINGLE | CHM_WHOLE_LAST_BUCKET, or 0 */
   double fixup_rel;       /* a projection p_r(x) = W_r.x - c_r (c_r = W_r.mu) is
                              recomputed in fp64 when its fp32 value v has
                              |v| < fixup_rel * (||W_r||_2 * ||x||_2 + |c_r|);
@@ -80,6 +80,12 @@ typedef struct chm_config {
  * second distance counts as infinite and the single candidate is accepted
  * (the other reading of Sec. 2.3.1 step (4)). */
 #define CHM_ACCEPT_SINGLE 1
+/* Flag of chm_config.flags.  Step (3) keeps the first K candidates in
+ * (Hamming distance, db index) order; with this flag every candidate as
+ * close in Hamming distance as the K-th is re-ranked as well (the other
+ * reading of checking buckets until K are returned).  The top-K keys
+ * written by a plan are the first K either way. */
+#define CHM_WHOLE_LAST_BUCKET 2
 
 /* Fills *cfg with the paper's defaults (L=6, m=8, K=8, t_r=4/5, BF16, 1e-4). */
 void chm_config_default(chm_config *cfg);

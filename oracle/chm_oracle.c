@@ -21,7 +21,9 @@
  *   - the candidates of a query are the SET union over tables of the db
  *     points sharing its bucket;
  *   - the top K are the min(K, |C|) candidates with the smallest
- *     (Hamming distance, db index) pairs in lexicographic order;
+ *     (Hamming distance, db index) pairs in lexicographic order; with
+ *     `whole` set (the other reading of "until K are returned") every
+ *     candidate as close as the K-th in Hamming distance is re-ranked too;
  *   - the ratio test dis(q1) < t_r * dis(q2) is taken on squared integer
  *     distances with t_r = a/b as b^2 d1 < a^2 d2; fewer than two candidates
  *     means no match, unless `single` is set: then a lone candidate has an
@@ -165,7 +167,7 @@ static int64_t sq_euclid(const uint8_t *x, const uint8_t *y) {
  * ranked candidates, 0xFFFFFFFF where fewer than K exist.  Returns the number of
  * (unique) candidates evaluated. */
 static int64_t match_pair_impl(const orc_image *q, const orc_image *d, int L, int m, int K,
-                               int ra, int rb, int single, int32_t *out, uint32_t *topk,
+                               int ra, int rb, int single, int whole, int32_t *out, uint32_t *topk,
                                int32_t *stamp, cand *buf) {
   const int nb = 1 << m;
   int64_t total = 0;
@@ -195,7 +197,10 @@ static int64_t match_pair_impl(const orc_image *q, const orc_image *d, int L, in
       for (int k = 0; k < K; ++k)
         topk[i * K + k] = k < nt ? ((uint32_t)buf[k].h << 24) | (uint32_t)buf[k].j : 0xFFFFFFFFu;
     }
-    /* (4) Euclidean re-rank of the top K and ratio test */
+    /* (4) Euclidean re-rank of the top K (or of every candidate within the
+       K-th's Hamming distance) and ratio test */
+    if (whole && nt > 0)
+      while (nt < nc && buf[nt].h == buf[nt - 1].h) ++nt;
     if (nt < 2) { out[i] = (nt == 1 && single) ? buf[0].j : -1; continue; }
     int64_t d1 = -1, d2 = -1;
     int32_t j1 = -1;
@@ -210,10 +215,11 @@ static int64_t match_pair_impl(const orc_image *q, const orc_image *d, int L, in
 }
 
 int64_t orc_match_pair(const orc_image *q, const orc_image *d, int32_t L, int32_t m, int32_t K,
-                       int32_t ra, int32_t rb, int32_t single, int32_t *out, uint32_t *topk) {
+                       int32_t ra, int32_t rb, int32_t single, int32_t whole, int32_t *out,
+                       uint32_t *topk) {
   int32_t *stamp = (int32_t *)malloc(sizeof(int32_t) * (size_t)(d->n > 0 ? d->n : 1));
   cand *buf = (cand *)malloc(sizeof(cand) * (size_t)(d->n > 0 ? d->n : 1));
-  int64_t c = match_pair_impl(q, d, L, m, K, ra, rb, single, out, topk, stamp, buf);
+  int64_t c = match_pair_impl(q, d, L, m, K, ra, rb, single, whole, out, topk, stamp, buf);
   free(stamp);
   free(buf);
   return c;
@@ -224,7 +230,8 @@ int64_t orc_match_pair(const orc_image *q, const orc_image *d, int32_t L, int32_
  * Returns the total number of candidates evaluated. */
 int64_t orc_match_pairs(const orc_image *images, const int32_t *pairs, int64_t P,
                         const int64_t *out_offsets, int32_t L, int32_t m, int32_t K,
-                        int32_t ra, int32_t rb, int32_t single, int32_t *out, uint32_t *topk) {
+                        int32_t ra, int32_t rb, int32_t single, int32_t whole, int32_t *out,
+                        uint32_t *topk) {
   int64_t nmax = 1;
   for (int64_t p = 0; p < P; ++p) {
     int64_t nd = images[pairs[2 * p + 1]].n;
@@ -238,7 +245,7 @@ int64_t orc_match_pairs(const orc_image *images, const int32_t *pairs, int64_t P
     int64_t p;
 #pragma omp for schedule(dynamic, 1)
     for (p = 0; p < P; ++p) {
-      total += match_pair_impl(&images[pairs[2 * p]], &images[pairs[2 * p + 1]], L, m, K, ra, rb, single,
+      total += match_pair_impl(&images[pairs[2 * p]], &images[pairs[2 * p + 1]], L, m, K, ra, rb, single, whole,
                                out + out_offsets[p],
                                topk ? topk + out_offsets[p] * K : NULL, stamp, buf);
     }

@@ -37,9 +37,10 @@ def lib():
         L.orc_project.argtypes = [vp, i64, vp, i32, vp, vp]
         L.orc_hash.argtypes = [vp, i64, vp, vp, i32, i32, vp, vp]
         L.orc_tables.argtypes = [vp, i64, i32, i32, vp, vp]
-        L.orc_match_pair.argtypes = [C.POINTER(_Image), C.POINTER(_Image), i32, i32, i32, i32, i32, i32, vp, vp]
+        L.orc_match_pair.argtypes = [C.POINTER(_Image), C.POINTER(_Image), i32, i32, i32, i32, i32, i32, i32, vp,
+                                     vp]
         L.orc_match_pair.restype = i64
-        L.orc_match_pairs.argtypes = [C.POINTER(_Image), vp, i64, vp, i32, i32, i32, i32, i32, i32, vp, vp]
+        L.orc_match_pairs.argtypes = [C.POINTER(_Image), vp, i64, vp, i32, i32, i32, i32, i32, i32, i32, vp, vp]
         L.orc_match_pairs.restype = i64
         L.orc_bruteforce.argtypes = [vp, i64, vp, i64, i32, i32, vp]
         L.orc_set_threads.argtypes = [C.c_int]
@@ -121,18 +122,20 @@ def hash_image(X: np.ndarray, W: np.ndarray, mu: np.ndarray, L: int, m: int) -> 
 
 
 def match_pair(q: Hashed, d: Hashed, L: int, m: int, K: int, ratio=(4, 5),
-               want_topk: bool = False, accept_single: bool = False):
+               want_topk: bool = False, accept_single: bool = False, whole_last_bucket: bool = False):
     """(matches (nq,) int32, topk keys (nq, K) uint32 or None, candidate count)."""
     out = np.zeros(q.n, dtype=np.int32)
     topk = np.zeros((q.n, K), dtype=np.uint32) if want_topk else None
     sq, sd = q.as_struct(), d.as_struct()
-    nc = lib().orc_match_pair(C.byref(sq), C.byref(sd), L, m, K, ratio[0], ratio[1], int(accept_single), _p(out),
+    nc = lib().orc_match_pair(C.byref(sq), C.byref(sd), L, m, K, ratio[0], ratio[1], int(accept_single),
+                              int(whole_last_bucket), _p(out),
                               _p(topk) if want_topk else None)
     return out, topk, int(nc)
 
 
 def match_pairs(images: Sequence[Hashed], pairs: np.ndarray, L: int, m: int, K: int,
-                ratio=(4, 5), want_topk: bool = False, accept_single: bool = False):
+                ratio=(4, 5), want_topk: bool = False, accept_single: bool = False,
+                whole_last_bucket: bool = False):
     """All directed pairs; returns (out concatenated, out_offsets (P+1), topk, candidates)."""
     pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
     P = pairs.shape[0]
@@ -144,6 +147,7 @@ def match_pairs(images: Sequence[Hashed], pairs: np.ndarray, L: int, m: int, K: 
     arr = (_Image * max(1, len(images)))(
         *[im.as_struct() if im is not None else _Image(0, 0, 0, 0, 0, 0) for im in images])
     nc = lib().orc_match_pairs(arr, _p(pairs), P, _p(offs), L, m, K, ratio[0], ratio[1], int(accept_single),
+                               int(whole_last_bucket),
                                _p(out), _p(topk) if want_topk else None)
     return out, offs, topk, int(nc)
 

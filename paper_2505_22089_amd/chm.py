@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(HERE, "libchm.so")
 
 ABI_VERSION = 1
 ACCEPT_SINGLE = 1
+WHOLE_LAST_BUCKET = 2
 PROJ_BF16, PROJ_FP32 = 0, 1
 MATCH_PLAIN, MATCH_BATCHED = 0, 1
 MAX_FEATS = 65535
@@ -149,14 +150,14 @@ def _stream(stream) -> Optional[int]:
 
 
 def config(L=6, m=8, K=8, ratio=(4, 5), precision=PROJ_BF16, fixup_rel=1e-4,
-           accept_single=False) -> Config:
+           accept_single=False, whole_last_bucket=False) -> Config:
     c = Config()
     lib().chm_config_default(C.byref(c))
     c.num_tables, c.bucket_bits, c.top_k = L, m, K
     c.ratio_num, c.ratio_den = ratio
     c.proj_precision = precision
     c.fixup_rel = fixup_rel
-    c.flags = ACCEPT_SINGLE if accept_single else 0
+    c.flags = (ACCEPT_SINGLE if accept_single else 0) | (WHOLE_LAST_BUCKET if whole_last_bucket else 0)
     return c
 
 

@@ -67,7 +67,8 @@ static chm_status check_config(const chm_config* c) {
     return fail(CHM_E_INVALID_ARG, "ratio must satisfy 0 < num <= den <= 46340");
   if (c->proj_precision != CHM_PROJ_BF16 && c->proj_precision != CHM_PROJ_FP32)
     return fail(CHM_E_INVALID_ARG, "proj_precision must be CHM_PROJ_BF16 or CHM_PROJ_FP32");
-  if (c->flags & ~CHM_ACCEPT_SINGLE) return fail(CHM_E_INVALID_ARG, "unknown config flags 0x%x", c->flags);
+  if (c->flags & ~(CHM_ACCEPT_SINGLE | CHM_WHOLE_LAST_BUCKET))
+    return fail(CHM_E_INVALID_ARG, "unknown config flags 0x%x", c->flags);
   if (!(c->fixup_rel >= 1e-4 && c->fixup_rel <= 0.5))
     return fail(CHM_E_INVALID_ARG, "fixup_rel must lie in [1e-4, 0.5]");
   return CHM_OK;
@@ -624,6 +625,7 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   a.ratio_num = S->cfg.ratio_num;
   a.ratio_den = S->cfg.ratio_den;
   a.accept_single = (S->cfg.flags & CHM_ACCEPT_SINGLE) ? 1 : 0;
+  a.whole_bucket = (S->cfg.flags & CHM_WHOLE_LAST_BUCKET) ? 1 : 0;
   a.lds_max_feats = ldsmax;
 
   if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {

@@ -61,6 +61,7 @@ struct MatchArgs {
   int32_t ratio_num;
   int32_t ratio_den;
   int32_t accept_single;  // a single candidate passes the ratio test
+  int32_t whole_bucket;   // re-rank every candidate as close as the K-th
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
 };
 

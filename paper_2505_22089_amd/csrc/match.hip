@@ -272,6 +272,73 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
         a.topk[o * a.K + k] = top[k] == kNoKey ? kNoKey : (top[k] & 0xFF000000u) | ((top[k] & 0xFFFFFFu) >> 4);
   }
 
+  if (a.whole_bucket) {  // uniform: the variant that re-ranks the K-th's whole tie class
+    // Hamming distance of the K-th candidate (or of the last, with fewer)
+    uint32_t hk = 0;
+    bool any = false;
+#pragma unroll
+    for (int k = 0; k < KT; ++k)
+      if (k < a.K && top[k] != kNoKey) {
+        hk = top[k] >> 24;
+        any = true;
+      }
+    uint32_t d1 = 0xFFFFFFFFu, d2 = 0xFFFFFFFFu;
+    int j1 = -1, cnt = 0;
+    if (valid && any) {
+      // a second walk over the query's buckets: each candidate once (pads
+      // repeat the bucket's first member; a candidate that shares the
+      // query's bucket in an earlier table was seen there), every one
+      // within hk re-ranked by exact distance
+      const uint4* xq = reinterpret_cast<const uint4*>(P.q.desc + (size_t)q * kDim);
+      const uint32_t nq = *(gcu32*)(P.q.norms + q);
+      for (int tt = 0; tt < a.L; ++tt) {
+        const uint32_t bq = ((tt < 4 ? qb0 >> (8 * tt) : qb1 >> (8 * (tt - 4)))) & 0xFFu;
+        const int s0 = offs[tt * stride + bq], s1 = offs[tt * stride + bq + 1];
+        if (s0 >= s1) continue;
+        const uint32_t tpos = (uint32_t)tt * (uint32_t)P.d.m_stride;
+        const uint32_t first = *(gcu32*)(mbase + 4u * (tpos + (uint32_t)s0));
+        for (int sp = s0; sp < s1; ++sp) {
+          const uint32_t w = *(gcu32*)(mbase + 4u * (tpos + (uint32_t)sp));
+          if (sp > s0 && w == first) continue;  // a pad
+          const uint4 c = (!LDSC && tcodes) ? ldg4(tcodes + 16u * (tpos + (uint32_t)sp)) : code_at<LDSC>(gcodes, w);
+          const uint32_t h = bcnt_acc(qc.w ^ c.w, bcnt_acc(qc.z ^ c.z, bcnt_acc(qc.y ^ c.y, bcnt_acc(qc.x ^ c.x, 0u))));
+          if (h > hk) continue;
+          const uint32_t j = w >> 4;
+          bool seen = false;
+          for (int t2 = 0; t2 < tt; ++t2) {
+            const uint32_t b2 = ((t2 < 4 ? qb0 >> (8 * t2) : qb1 >> (8 * (t2 - 4)))) & 0xFFu;
+            seen |= *(gcu8*)(P.d.ids + (size_t)t2 * P.d.n_pad + j) == b2;
+          }
+          if (seen) continue;
+          const uint4* yp = reinterpret_cast<const uint4*>(P.d.desc + (size_t)j * kDim);
+          uint32_t dot = 0;
+#pragma unroll
+          for (int v = 0; v < 8; ++v) {
+            const uint4 x = ldg4(xq + v), y = ldg4(yp + v);
+            dot = __builtin_amdgcn_udot4(x.x, y.x, dot, false);
+            dot = __builtin_amdgcn_udot4(x.y, y.y, dot, false);
+            dot = __builtin_amdgcn_udot4(x.z, y.z, dot, false);
+            dot = __builtin_amdgcn_udot4(x.w, y.w, dot, false);
+          }
+          const uint32_t e2 = nq + *(gcu32*)(P.d.norms + j) - 2u * dot;
+          if (e2 < d1 || (e2 == d1 && (int)j < j1)) {  // candidate order: by distance, then index
+            d2 = d1;
+            d1 = e2;
+            j1 = (int)j;
+          } else {
+            d2 = min(d2, e2);
+          }
+          ++cnt;
+        }
+      }
+    }
+    const bool pass = cnt >= 2 ? (uint64_t)a.ratio_den * (uint64_t)a.ratio_den * d1 <
+                                     (uint64_t)a.ratio_num * (uint64_t)a.ratio_num * d2
+                               : cnt == 1 && a.accept_single != 0;
+    if (valid) a.out[o] = pass ? j1 : -1;
+    return;
+  }
+
   // Exact re-rank of the first K candidates and ratio test, with the
   // wavefront's lanes in groups of kRerankLanes: in round g, group r serves
   // the query of lane (64 / kRerankLanes) g + r, each of its lanes reading

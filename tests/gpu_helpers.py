@@ -11,10 +11,11 @@ def device():
 
 
 def new_store(wl, precision=chm.PROJ_BF16, K=None, L=None, m=None, extra=64 << 20, fixup_rel=1e-4,
-              accept_single=False):
+              accept_single=False, whole_last_bucket=False):
     cfg = chm.config(L=wl.L if L is None else L, m=wl.m if m is None else m,
                      K=wl.K if K is None else K, ratio=wl.ratio, precision=precision,
-                     fixup_rel=fixup_rel, accept_single=accept_single)
+                     fixup_rel=fixup_rel, accept_single=accept_single,
+                     whole_last_bucket=whole_last_bucket)
     need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256
                                                for x in wl.images) + extra
     arena = torch.empty(need, dtype=torch.uint8, device=device())

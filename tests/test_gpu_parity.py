@@ -116,7 +116,8 @@ def check_matches(st, wl, pairs, mode, K):
                                     wl.mu, st.cfg.num_tables, st.cfg.bucket_bits)
         ro, rt, _ = O.match_pair(H[q], H[d], st.cfg.num_tables, st.cfg.bucket_bits, K,
                                  wl.ratio, want_topk=True,
-                                 accept_single=bool(st.cfg.flags & chm.ACCEPT_SINGLE))
+                                 accept_single=bool(st.cfg.flags & chm.ACCEPT_SINGLE),
+                                 whole_last_bucket=bool(st.cfg.flags & chm.WHOLE_LAST_BUCKET))
         a, b = offs[p], offs[p + 1]
         assert np.array_equal(topk[a:b], rt), "top-K keys of pair %d (%d -> %d)" % (p, q, d)
         assert np.array_equal(out[a:b], ro), "matches of pair %d (%d -> %d)" % (p, q, d)
@@ -141,6 +142,21 @@ def test_match_parity_accept_single(mode):
     st = new_store(wl, L=2, accept_single=True)
     load_all(st, wl.images)
     out = check_matches(st, wl, [(0, 1), (0, 2), (0, 3), (1, 0)], mode, wl.K)
+    assert (out >= 0).any()
+    st.close()
+
+
+@pytest.mark.parametrize("mode,L,m,K,lds", [(chm.MATCH_PLAIN, 3, 5, 4, 1), (chm.MATCH_BATCHED, 3, 5, 4, 1),
+                                            (chm.MATCH_BATCHED, 6, 8, 8, 0), (chm.MATCH_BATCHED, 2, 3, 2, 1)])
+def test_match_parity_whole_last_bucket(mode, L, m, K, lds):
+    """The other reading of step (3): every candidate as close in Hamming
+    distance as the K-th is re-ranked.  Few bucket bits make wide tie
+    classes; lds 0 reads the codes from HBM."""
+    wl = small_workload([700, 500, 300, 40], seed=41, L=L, m=m, K=K)
+    st = new_store(wl, whole_last_bucket=True)
+    st.set_tuning(lds_codes=lds)
+    load_all(st, wl.images)
+    out = check_matches(st, wl, [(0, 1), (1, 0), (2, 3), (0, 0)], mode, K)
     assert (out >= 0).any()
     st.close()
 

@@ -253,6 +253,41 @@ def two_nn_ratio(Xq, Xd, a, b):
     return out
 
 
+@pytest.mark.parametrize("m,K", [(8, 2), (3, 4), (5, 8)])
+def test_whole_last_bucket_matches_dense_formulation(orc, small, m, K):
+    """The other reading of "until K are returned": every candidate as close
+    in Hamming distance as the K-th is re-ranked.  Expected result: dense
+    candidate sets, the tie class of the K-th, then exact 2-NN + ratio test
+    over it with SciPy's distances."""
+    A, B, W0, mu = small
+    A, B = A[:150], B[:200]
+    W = W0[:128 + L * m]
+    hq = orc.hash_image(A, W, mu, L, m)
+    hd = orc.hash_image(B, W, mu, L, m)
+    out, _, _ = orc.match_pair(hq, hd, L, m, K, whole_last_bucket=True)
+    qi = [code_int(c) for c in hq.codes]
+    di = [code_int(c) for c in hd.codes]
+    D = cdist(A.astype(np.float64), B.astype(np.float64), "sqeuclidean").astype(np.int64)
+    ties = 0
+    for i in range(len(A)):
+        cand = np.nonzero((hq.ids[i][None, :] == hd.ids).any(axis=1))[0]
+        keys = sorted((bin(qi[i] ^ di[j]).count("1"), j) for j in cand)
+        if keys:
+            hk = keys[min(K, len(keys)) - 1][0]
+            T = [j for h, j in keys if h <= hk]
+            ties += len(T) > K
+        else:
+            T = []
+        expect = -1
+        if len(T) >= 2:
+            order = sorted(T, key=lambda j: (D[i, j], j))
+            d1, d2 = D[i, order[0]], D[i, order[1]]
+            if 25 * d1 < 16 * d2:
+                expect = order[0]
+        assert out[i] == expect, i
+    assert ties > 0  # the variant differs from top-K somewhere
+
+
 def test_single_bucket_reduces_to_exhaustive_2nn(orc, small):
     A, B, W, mu = small
     Wm = W[:128]
