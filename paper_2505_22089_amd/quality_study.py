@@ -3,7 +3,9 @@
 For the 50-image workload (tracks planted by the footprint model), runs the
 batched GPU matcher for a grid of K (candidates kept, Sec. 2.3.1 step (3))
 and ratio thresholds t_r (step (4)), with and without a mutual check
-(i -> j kept only if j -> i is also returned by the reverse pair), and
+(i -> j kept only if j -> i is also returned by the reverse pair), with the
+two other readings of the method (the whole tie class of the K-th candidate
+re-ranked; a lone candidate accepted), and
 scores precision and recall against the ground truth: a match i -> j is
 correct when descriptor i of the query and j of the db image observe the
 same track.  Recall counts the query descriptors whose track the db image
@@ -61,17 +63,22 @@ def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, 
     rows = []
     for K in Ks:
         for ra in ratios:
-            cfg = chm.config(L=L, m=m, K=K, ratio=ra)
-            need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256
-                                                       for x in wl.images)
-            arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device=dev)
-            st = chm.Store(cfg, wl.W[:128 + L * m], wl.mu, arena)
-            st.load(list(range(len(wl.images))), descs)
-            offs = chm.out_offsets(st, pairs)
-            out_t = torch.empty(int(offs[-1]), dtype=torch.int32, device=dev)
-            chm.match_pairs(st, pairs, out_t, chm.MATCH_BATCHED, offs=offs)
-            out = out_t.cpu().numpy()
-            st.close()
+            variants = {}
+            for name, flags in (("plain", {}), ("whole last bucket", {"whole_last_bucket": True}),
+                                ("accept single", {"accept_single": True})):
+                cfg = chm.config(L=L, m=m, K=K, ratio=ra, **flags)
+                need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256
+                                                           for x in wl.images)
+                arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device=dev)
+                st = chm.Store(cfg, wl.W[:128 + L * m], wl.mu, arena)
+                st.load(list(range(len(wl.images))), descs)
+                offs = chm.out_offsets(st, pairs)
+                out_t = torch.empty(int(offs[-1]), dtype=torch.int32, device=dev)
+                chm.match_pairs(st, pairs, out_t, chm.MATCH_BATCHED, offs=offs)
+                variants[name] = out_t.cpu().numpy()
+                st.close()
+                del arena
+            out = variants["plain"]
             # mutual check on the pairs whose reverse pair is listed
             keep = []
             for p, (q, d) in enumerate(pairs):
@@ -85,7 +92,9 @@ def run(Ks=(2, 4, 8, 16), ratios=((1, 2), (3, 5), (7, 10), (4, 5)), L: int = 6, 
                 ok[ok] = md[mq[ok]] == np.nonzero(ok)[0]
                 keep.append(ok)
             row = {"K": K, "ratio": "%d/%d" % ra, "repeat_frac": repeat_frac,
-                   "plain": _score(wl, pairs, offs, out), "mutual": _score(wl, pairs, offs, out, keep)}
+                   "plain": _score(wl, pairs, offs, out), "mutual": _score(wl, pairs, offs, out, keep),
+                   "whole last bucket": _score(wl, pairs, offs, variants["whole last bucket"]),
+                   "accept single": _score(wl, pairs, offs, variants["accept single"])}
             for th in sao_thresholds:
                 f = chm.sao_filter(kps, pairs, offs, out, 6, th)
                 row["sao %d/%d" % th] = _score(wl, pairs, offs, f)
