@@ -248,3 +248,20 @@ def test_hash_parity_when_fixup_list_overflows():
         check_hash(st, wl, [0, 1])
         assert st.stats().fixups >= 377 * 176
         st.close()
+
+
+def test_match_parity_stored_golden_pair():
+    """The HIP path reproduces the stored oracle matches of the small golden
+    pair (written by tests/golden/make_golden.py)."""
+    import os
+    from tests.golden import make_golden as G
+    A, B, W, mu = G.match_case()
+    path = os.path.join(os.path.dirname(__file__), "golden", "match_pair_300.txt")
+    expect = np.array([int(v) for l in open(path) if not l.startswith("#") for v in l.split()])
+    wl = synth.Workload(name="golden", images=[A, B], pairs=np.array([[0, 1]], np.int32), W=W, mu=mu)
+    for mode in (chm.MATCH_PLAIN, chm.MATCH_BATCHED):
+        st = new_store(wl)
+        load_all(st, wl.images)
+        out, _, _ = run_match(st, [(0, 1)], mode)
+        assert np.array_equal(out, expect)
+        st.close()

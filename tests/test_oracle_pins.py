@@ -362,3 +362,17 @@ def test_empty_and_single_images(orc, small):
     assert np.all(out == -1)
     out, _, _ = orc.match_pair(h0, hq, L, M, 8)
     assert out.shape == (0,)
+
+
+def test_stored_golden_pair_still_matches_the_oracle(orc):
+    """The stored values under tests/golden/ were written by the oracle; any
+    later change to its arithmetic must show here (and name its reason)."""
+    import os
+    from tests.golden import make_golden as G
+    A, B, W, mu = G.match_case()
+    path = os.path.join(os.path.dirname(__file__), "golden", "match_pair_300.txt")
+    expect = np.array([int(v) for l in open(path) if not l.startswith("#") for v in l.split()])
+    hq, hd = orc.hash_image(A, W, mu, 6, 8), orc.hash_image(B, W, mu, 6, 8)
+    out, _, _ = orc.match_pair(hq, hd, 6, 8, 8, (4, 5))
+    assert np.array_equal(out, expect)
+    assert (expect >= 0).sum() > 100

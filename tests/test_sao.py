@@ -232,3 +232,22 @@ def test_device_entry_rejects_bad_arguments_before_any_gpu_call():
     need = chm.sao_work_bytes(1, 10)
     assert call(work_bytes=need - 1) == -3             # CHM_E_CAPACITY
     assert chm.sao_work_bytes(400, 8000) < (1 << 30)
+
+
+def _golden(name):
+    import os
+    lines = [l for l in open(os.path.join(os.path.dirname(__file__), "golden", name)) if not l.startswith("#")]
+    return [np.array([int(v) for v in l.split()]) for l in lines]
+
+
+def test_stored_sao_values_still_hold_for_oracle_and_library():
+    from tests.golden import make_golden as G
+    kq, kd, match = G.sao_case()
+    ced, filt = _golden("sao_60.txt")
+    rc, rf = S.sao_pair(kq, kd, match, 6, (1, 2))
+    assert np.array_equal(rc, ced) and np.array_equal(rf, filt)
+    out, lc = chm.sao_filter([kq, kd], np.array([[0, 1]]), np.array([0, 60], np.int64), match, 6, (1, 2),
+                             want_ced=True)
+    assert np.array_equal(lc, ced) and np.array_equal(out, filt)
+    # the random matches are all rejected, most of the transformed ones kept
+    assert (filt[45:] == -1).all() and (filt[:45] >= 0).mean() > 0.7
