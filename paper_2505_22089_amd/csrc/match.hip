@@ -20,7 +20,11 @@
 //  (4) for the first K kept candidates it computes the exact squared distance
 //      ||x||^2 + ||y||^2 - 2 x.y with packed-u8 dot products and int32
 //      accumulation, and applies the ratio test on squared distances
-//      (den^2 * d1 < num^2 * d2).
+//      (den^2 * d1 < num^2 * d2).  The lanes of the wavefront share this
+//      step: groups of kRerankLanes lanes read whole candidate descriptors
+//      for one query at a time.  Two other readings are flags: a lone
+//      candidate accepted, and the whole tie class of the K-th candidate
+//      re-ranked (a second, per-lane walk).
 //
 // Work items are (pair, query range); an item's queries are taken in order
 // of walk length, so the lanes of a wavefront walk about as far.  Batched
@@ -29,8 +33,9 @@
 // data stays in that XCD's L2); inside a work-group, wavefronts take
 // 64-query chunks of the item dynamically.  Plain plans launch one grid per
 // pair.  With LDSC the db image's codes and bucket offsets are staged in LDS
-// once per item (skipped when consecutive items share the db image); larger
-// db images are read from their bucket-ordered code copy.
+// once per item (skipped when consecutive items share the db image); db
+// images too large for the stage are read from their bucket-ordered code
+// copy, in the same launch.
 #include "chm_internal.h"
 
 namespace chm {
