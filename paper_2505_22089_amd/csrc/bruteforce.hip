@@ -26,8 +26,18 @@ typedef int32_t i32x4v __attribute__((ext_vector_type(4)));
 typedef int32_t i32x16v __attribute__((ext_vector_type(16)));
 typedef uint32_t u32x4v __attribute__((ext_vector_type(4)));
 
-constexpr int kBfWaves = 4;
-constexpr int kBfQ = 32 * kBfWaves;  // queries per work-group
+#ifndef CHM_BF_WAVES
+#define CHM_BF_WAVES 8
+#endif
+constexpr int kBfWaves = CHM_BF_WAVES;  // waves per work-group
+// 32-query row blocks per wave: each staged db fragment feeds that many
+// independent MFMA chains, which halves LDS reads per multiply-add at 2
+#ifndef CHM_BF_ROWBLOCKS
+#define CHM_BF_ROWBLOCKS 1
+#endif
+constexpr int kBfRB = CHM_BF_ROWBLOCKS;
+constexpr int kBfQ = 32 * kBfRB * kBfWaves;  // queries per work-group
+static_assert(kBfWaves >= 4, "the 256 tile stagers are whole waves of the work-group");
 constexpr int kBfD = 128;            // db rows per LDS tile
 constexpr int kBfStride = 144;       // bytes per staged row (pad spreads banks)
 constexpr int kBfTargetWG = 1024;    // aim for this many work-groups (splits of the db)
@@ -47,7 +57,7 @@ __device__ __forceinline__ void merge2(int32_t& s1, int32_t& j1, int32_t& s2, in
   j1 = nj;
 }
 
-__global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, const uint8_t* D,
+__global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, int nq, const uint8_t* D,
                                                     int nd, int split_cols, int4* work) {
   __shared__ __attribute__((aligned(16))) uint8_t sD[kBfD * kBfStride];
   __shared__ int32_t sN[kBfD];
@@ -55,21 +65,26 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
   const int wave = tid >> 6;
   const int lane = __lane_id();
   const int half = lane >> 5;
-  const int qr = blockIdx.x * kBfQ + wave * 32 + (lane & 31);
+  const int qbase = blockIdx.x * kBfQ + wave * 32 * kBfRB;  // the wave's first query row
   const int c0 = blockIdx.y * split_cols;
   const int c1 = min(nd, c0 + split_cols);
 
-  i32x4v A[4];
+  i32x4v A[kBfRB][4];
 #pragma unroll
-  for (int ks = 0; ks < 4; ++ks) {
-    u32x4v v = {0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
-    if (qr < nq) v = *reinterpret_cast<const u32x4v*>(Q + (size_t)qr * kDim + 32 * ks + 16 * half);
-    v ^= 0x80808080u;
-    A[ks] = __builtin_bit_cast(i32x4v, v);
+  for (int rb = 0; rb < kBfRB; ++rb) {
+    const int qr = qbase + 32 * rb + (lane & 31);
+#pragma unroll
+    for (int ks = 0; ks < 4; ++ks) {
+      u32x4v v = {0x80808080u, 0x80808080u, 0x80808080u, 0x80808080u};
+      if (qr < nq) v = *reinterpret_cast<const u32x4v*>(Q + (size_t)qr * kDim + 32 * ks + 16 * half);
+      v ^= 0x80808080u;
+      A[rb][ks] = __builtin_bit_cast(i32x4v, v);
+    }
   }
-  int32_t s1[16], s2[16], t1[16];  // best and second keys, tile of the best
+  constexpr int E = 16 * kBfRB;  // accumulator elements per lane
+  int32_t s1[E], s2[E], t1[E];   // best and second keys, tile of the best
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
+  for (int e = 0; e < E; ++e) {
     s1[e] = INT_MIN;
     s2[e] = INT_MIN;
     t1[e] = -1;
@@ -77,8 +92,9 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
 
   for (int tile = c0; tile < c1; tile += kBfD) {
     __syncthreads();
-    {
-      // thread stages half a row: 64 bytes as four 16-byte pieces
+    // the first 256 threads stage the tile, half a row each: 64 bytes as
+    // four 16-byte pieces (whole waves, so the shuffle below is uniform)
+    if (tid < 2 * kBfD) {
       const int row = tid >> 1, part = tid & 1;
       const int g = tile + row;
       int32_t nrm = 0;
@@ -97,42 +113,49 @@ __global__ __launch_bounds__(256) void k_bf_partial(const uint8_t* Q, int nq, co
       if (part == 0) sN[row] = (g < c1) ? -(nrm << 7) + (127 - row) : -(1 << 30);
     }
     __syncthreads();
-    int32_t before[16];
+    int32_t before[E];
 #pragma unroll
-    for (int e = 0; e < 16; ++e) before[e] = s1[e];
+    for (int e = 0; e < E; ++e) before[e] = s1[e];
 #pragma unroll
     for (int blk = 0; blk < kBfD / 32; ++blk) {
       const int crow = blk * 32 + (lane & 31);
-      i32x16v acc = {};
+      i32x16v acc[kBfRB];
+#pragma unroll
+      for (int rb = 0; rb < kBfRB; ++rb) acc[rb] = i32x16v{};
 #pragma unroll
       for (int ks = 0; ks < 4; ++ks) {
         const i32x4v B = *reinterpret_cast<const i32x4v*>(sD + crow * kBfStride + 32 * ks + 16 * half);
-        acc = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[ks], B, acc, 0, 0, 0);
+#pragma unroll
+        for (int rb = 0; rb < kBfRB; ++rb)
+          acc[rb] = __builtin_amdgcn_mfma_i32_32x32x32_i8(A[rb][ks], B, acc[rb], 0, 0, 0);
       }
       const int32_t bias = sN[crow];
 #pragma unroll
-      for (int e = 0; e < 16; ++e) {
-        const int32_t key = (acc[e] << 8) + bias;  // 128 (2 x'.y' - ||y'||^2) + 127 - c
-        s2[e] = med3i(s1[e], s2[e], key);
-        s1[e] = max(s1[e], key);
+      for (int rb = 0; rb < kBfRB; ++rb) {
+#pragma unroll
+        for (int e = 0; e < 16; ++e) {
+          const int32_t key = (acc[rb][e] << 8) + bias;  // 128 (2 x'.y' - ||y'||^2) + 127 - c
+          s2[16 * rb + e] = med3i(s1[16 * rb + e], s2[16 * rb + e], key);
+          s1[16 * rb + e] = max(s1[16 * rb + e], key);
+        }
       }
     }
 #pragma unroll
-    for (int e = 0; e < 16; ++e) t1[e] = s1[e] != before[e] ? tile : t1[e];
+    for (int e = 0; e < E; ++e) t1[e] = s1[e] != before[e] ? tile : t1[e];
   }
   // merge the 32 lanes that hold the same query rows (lanes of one half);
   // from here on a best key travels with its global column
-  int32_t j1[16];
+  int32_t j1[E];
 #pragma unroll
-  for (int e = 0; e < 16; ++e) j1[e] = s1[e] == INT_MIN ? -1 : t1[e] + (127 - (s1[e] & 127));
+  for (int e = 0; e < E; ++e) j1[e] = s1[e] == INT_MIN ? -1 : t1[e] + (127 - (s1[e] & 127));
 #pragma unroll
-  for (int e = 0; e < 16; ++e) {
+  for (int e = 0; e < E; ++e) {
 #pragma unroll
     for (int d = 1; d < 32; d <<= 1) {
       const int32_t u = __shfl_xor(s1[e], d), uj = __shfl_xor(j1[e], d), u2 = __shfl_xor(s2[e], d);
       merge2(s1[e], j1[e], s2[e], u, uj, u2);
     }
-    const int row = blockIdx.x * kBfQ + wave * 32 + 8 * (e >> 2) + 4 * half + (e & 3);
+    const int row = qbase + 32 * (e >> 4) + 8 * ((e & 15) >> 2) + 4 * half + (e & 3);
     if ((lane & 31) == 0 && row < nq) work[(size_t)blockIdx.y * nq + row] = make_int4(s1[e], j1[e], s2[e], 0);
   }
 }
@@ -179,7 +202,7 @@ hipError_t launch_bruteforce(const uint8_t* q, int nq, const uint8_t* d, int nd,
   const int split_cols = ((dt + splits - 1) / splits) * kBfD;
   int4* w = reinterpret_cast<int4*>(work);
   if (nd > 0) {
-    hipLaunchKernelGGL(k_bf_partial, dim3((nq + kBfQ - 1) / kBfQ, splits), dim3(256), 0, s, q, nq,
+    hipLaunchKernelGGL(k_bf_partial, dim3((nq + kBfQ - 1) / kBfQ, splits), dim3(64 * kBfWaves), 0, s, q, nq,
                        d, nd, split_cols, w);
   }
   hipLaunchKernelGGL(k_bf_merge, dim3((nq + 255) / 256), dim3(256), 0, s, w, nd > 0 ? splits : 0, q,
