@@ -205,6 +205,11 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
     int nx = 1;
     if (hipDeviceGetAttribute(&nx, hipDeviceAttributeNumberOfXccs, dev) != hipSuccess || nx < 1) nx = 1;
     S->n_xcd = std::min(nx, kMaxBins);
+    // the match kernel's LDS stage takes what one work-group may have
+    int lds = 0;
+    if (hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lds = 0;
+    lds = std::min<int>(lds, (int)kLdsTotal);
+    S->lds_top = std::max(0, lds - (int)kLdsTop) & ~15;
   }
   S->device = dev;
   S->arena.free_[kHdrBytes] = arena_bytes - kHdrBytes;
@@ -464,7 +469,7 @@ extern "C" chm_status chm_store_set_tuning(chm_store* S, const chm_tuning* t) {
 // ------------------------------------------------------------------ plans
 
 int chm::lds_max_feats(const chm_store* S) {
-  return lds_code_cap(S->cfg.num_tables, S->cfg.bucket_bits);
+  return std::min(lds_code_cap(), S->lds_top / 16);
 }
 
 static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
@@ -485,7 +490,7 @@ static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
 
 chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
                            int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream,
-                           chm_plan** out) {
+                           chm_plan** out, bool wait_upload) {
   if (mode != CHM_MATCH_PLAIN && mode != CHM_MATCH_BATCHED) return fail(CHM_E_INVALID_ARG, "bad mode");
   std::vector<PairDev> pd(P);
   std::unordered_map<int32_t, uint64_t> gens;
@@ -544,8 +549,16 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
     for (int p = 0; p < P; ++p) {
       const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
       pl->lds_launch |= lds;
-      for (int q0 = 0; q0 < pd[p].q.n; q0 += qpi) {
-        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qpi), lds ? 1 : 0};
+      // Above a large stage an item's sort order may not fit: such pairs
+      // take items small enough to sort, down to one query per thread of a
+      // 1024-thread work-group; below that they keep full items, unsorted.
+      int qp = qpi;
+      if (lds) {
+        const int room = lds_sort_room(S->lds_top, pd[p].d.n) / 64 * 64;
+        if (room < qp && room >= 1024) qp = room;
+      }
+      for (int q0 = 0; q0 < pd[p].q.n; q0 += qp) {
+        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0};
         const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
         groups[pd[p].d.codes].push_back({cost, w});
       }
@@ -595,15 +608,25 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   pl->dItems = (WorkItem*)(S->base + pl->mem_off + pairs_bytes);
   pl->dQueue = (uint32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes);
   pl->dBins = (int32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes + queue_bytes);
-  const int32_t* hbins = pl->bins;
+  // the plan owns the host sources of its upload (and its bin table), so the
+  // copies may still be in flight when this call returns
+  pl->h_pairs = std::move(pd);
+  pl->h_items = std::move(items);
   hipStream_t s = (hipStream_t)stream;
+  pl->upload_stream = s;
+  pl->upload_pending = true;
   hipError_t e = hipSuccess;
-  if (P) e = hipMemcpyAsync(pl->dPairs, pd.data(), sizeof(PairDev) * P, hipMemcpyHostToDevice, s);
+  if (P) e = hipMemcpyAsync(pl->dPairs, pl->h_pairs.data(), sizeof(PairDev) * P, hipMemcpyHostToDevice, s);
   if (e == hipSuccess && pl->n_items)
-    e = hipMemcpyAsync(pl->dItems, items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, hbins, sizeof pl->bins, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);
+    e = hipMemcpyAsync(pl->dItems, pl->h_items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice,
+                       s);
+  if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, pl->bins, sizeof pl->bins, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && wait_upload) {
+    e = hipStreamSynchronize(s);
+    pl->upload_pending = false;
+  }
   if (e != hipSuccess) {
+    (void)hipStreamSynchronize(s);
     S->arena.release(pl->mem_off, pl->mem_bytes);
     delete pl;
     return fail(CHM_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
@@ -627,6 +650,7 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   a.accept_single = (S->cfg.flags & CHM_ACCEPT_SINGLE) ? 1 : 0;
   a.whole_bucket = (S->cfg.flags & CHM_WHOLE_LAST_BUCKET) ? 1 : 0;
   a.lds_max_feats = ldsmax;
+  a.lds_top = S->lds_top;
 
   if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {
     hipStream_t cs = S->cap_stream;
@@ -648,6 +672,7 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
     if (e == hipSuccess) e = hipGraphInstantiate(&pl->exec, g, nullptr, nullptr, 0);
     if (g) (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
+      if (pl->upload_pending) (void)hipStreamSynchronize(s);
       S->arena.release(pl->mem_off, pl->mem_bytes);
       delete pl;
       return fail(CHM_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
@@ -705,12 +730,18 @@ extern "C" chm_status chm_plan_execute(chm_plan* pl, void* stream) {
   return CHM_OK;
 }
 
-extern "C" void chm_plan_destroy(chm_plan* pl) {
+void chm::plan_free(chm_plan* pl) {
   if (!pl) return;
-  if (pl->executed) (void)hipStreamSynchronize(pl->last_stream);
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   pl->st->arena.release(pl->mem_off, pl->mem_bytes);
   delete pl;
+}
+
+extern "C" void chm_plan_destroy(chm_plan* pl) {
+  if (!pl) return;
+  if (pl->upload_pending) (void)hipStreamSynchronize(pl->upload_stream);
+  if (pl->executed) (void)hipStreamSynchronize(pl->last_stream);
+  plan_free(pl);
 }
 
 extern "C" chm_status chm_match_pairs(chm_store* S, const int32_t* h_pairs, int32_t P,

@@ -53,6 +53,7 @@ struct chm_store {
   chm_tuning tuning;
   int n_cu = 0;
   int n_xcd = 1;  // XCDs of the device (work-groups are dealt to them round-robin)
+  int lds_top = 0;  // byte address of the match kernel's LDS control words
   int device = 0;
   hipStream_t cap_stream = nullptr;
 };
@@ -81,12 +82,25 @@ struct chm_plan {
   hipGraphExec_t exec = nullptr;
   hipStream_t last_stream = nullptr;
   bool executed = false;
+  // Host sources of the plan's device lists.  A plan whose upload was not
+  // waited for keeps them until the upload stream has passed it.
+  std::vector<chm::PairDev> h_pairs;
+  std::vector<chm::WorkItem> h_items;
+  hipStream_t upload_stream = nullptr;
+  bool upload_pending = false;
 };
 
 namespace chm {
 HashImage hash_image_of(const chm_store* S, const ImageSlot& sl);
 chm_status hash_images(chm_store* S, const std::vector<const ImageSlot*>& slots, hipStream_t s);
 int lds_max_feats(const chm_store* S);
+// Builds a plan and queues its upload on `stream`.  With wait_upload the
+// call returns once the upload is done (the plan may then run on any
+// stream); without it the plan must run on `stream`, and plan_free() may be
+// called only once that stream has passed the plan's last launch.
 chm_status plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
-                      int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream, chm_plan** out);
+                      int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream, chm_plan** out,
+                      bool wait_upload = true);
+// Releases a plan without waiting: the caller has seen its work finish.
+void plan_free(chm_plan* pl);
 }  // namespace chm

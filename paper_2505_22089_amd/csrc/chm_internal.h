@@ -63,6 +63,7 @@ struct MatchArgs {
   int32_t accept_single;  // a single candidate passes the ratio test
   int32_t whole_bucket;   // re-rank every candidate as close as the K-th
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
+  int32_t lds_top;        // LDS-staging launches: byte address of the control words
 };
 
 // Device SAO (sao_device.hip).  h_starts[p] is where pair p's query rows
@@ -74,19 +75,35 @@ hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* co
                       const int32_t* h_n_feats, const int64_t* h_starts, const int32_t* d_match, int32_t nn,
                       int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work, bool clear_errors,
                       hipStream_t s);
+// The same in two parts: sao_upload writes the pair table (pairs 0..n-1 of
+// the work buffer's table) and returns once it is on the device; sao_run
+// filters table entries first..first+count-1 with at most n_max query rows
+// each, the table holding table_pairs entries (the scratch follows it).
+hipError_t sao_upload(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_starts, void* d_work, hipStream_t s);
+hipError_t sao_run(int32_t first, int32_t count, int32_t table_pairs, int32_t n_max, const int32_t* d_match,
+                   int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
+                   hipStream_t s);
 
-// Items of at most kSortMax queries are processed in order of walk length.
-// LDS after the staged codes and offsets: two control words (16 B), the
-// sort's histogram (256 u32), order (u16) and lengths (u8).
+// LDS of the match kernel.  The LDS-staging kernel takes all of a CU's LDS:
+// the db image's codes from address 0 (a code's LDS address is its member
+// value 16 j), then its bucket offsets when they fit beside a full-size sort
+// (else the walk reads them from L2), and at the top, from lds_top, two
+// control words (16 B) and the sort histogram (256 u32).  An item's sort
+// order (u16 per query) sits right below lds_top; an item of at most
+// kSortMax queries is processed in order of walk length when its order fits
+// above the stage, else in query order.  The HBM-only kernel's LDS is the
+// order array and the top.
 constexpr int kSortMax = 2048;
-constexpr size_t kMatchLdsTail = 16 + 256 * 4 + kSortMax * 3;
-constexpr size_t kLdsBudget = 160 * 1024 - 1024;  // a CU's LDS less a reserve
+constexpr size_t kLdsTop = 16 + 256 * 4;
+constexpr size_t kMatchLdsTail = 2 * kSortMax + kLdsTop;
+constexpr size_t kLdsTotal = 160 * 1024;
 
-// Codes the match kernel can stage in LDS for a db image: what is left of
-// the LDS after the bucket offsets and the kernel's control words and sort.
-__host__ __device__ constexpr int lds_code_cap(int L, int m) {
-  return (int)((kLdsBudget - ((size_t)L * ((1u << m) + 1) + 3) / 4 * 16 - kMatchLdsTail) / 16);
-}
+// Largest db image whose codes the LDS stage can hold.
+__host__ __device__ constexpr int lds_code_cap() { return (int)((kLdsTotal - kLdsTop) / 16); }
+// Queries of an item that can be sorted above a stage of n codes whose
+// offsets stay in L2 (lds_top bytes below the top words).
+__host__ __device__ constexpr int lds_sort_room(int lds_top, int n) { return (lds_top - 16 * n) / 2; }
 
 // Sections of one image slot in the arena (byte offsets from the slot
 // start, each 256-byte aligned): descriptors n x 128, long codes n x 16,
@@ -118,7 +135,7 @@ __host__ __device__ inline ImageLayout image_layout(int L, int m, int n) {
   l.norms = o;   o += layout_round((uint64_t)n * 4, 256);
   l.offsets = o; o += layout_round((uint64_t)L * (nb + 1) * 4, 256);
   l.members = o; o += layout_round((uint64_t)L * l.m_stride * 4, 256);
-  l.has_tcodes = n > lds_code_cap(L, m);
+  l.has_tcodes = n > lds_code_cap();
   l.tcodes = o;  o += l.has_tcodes ? layout_round((uint64_t)L * l.m_stride * 16, 256) : 0;
   l.total = o;
   return l;
@@ -202,7 +219,7 @@ hipError_t launch_buckets(const HashBatch& hb, hipStream_t s);
 hipError_t launch_match(const MatchArgs& a, int K, int wg, bool lds, bool persistent, int grid,
                         hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
-size_t match_lds_bytes(int lds_max_feats, int L, int nb);
+
 hipError_t launch_bruteforce(const uint8_t* q, int nq, const uint8_t* d, int nd, int ra, int rb,
                              int32_t* out, void* work, int splits, hipStream_t s);
 int bruteforce_splits(int nq, int nd);

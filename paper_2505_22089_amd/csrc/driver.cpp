@@ -22,6 +22,23 @@ struct SaoStep {
   int32_t nn, num, den;
   int32_t* d_filtered;
   void* d_work;
+  uint64_t work_bytes;
+};
+
+// Plans still read by queued work, and the events that mark their ends.  On
+// the way out (normal or not) the stream is drained before anything is freed.
+struct InFlight {
+  hipStream_t s;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  chm_plan* pl[2] = {nullptr, nullptr};
+  explicit InFlight(hipStream_t st) : s(st) {}
+  ~InFlight() {
+    if (pl[0] || pl[1]) (void)hipStreamSynchronize(s);
+    plan_free(pl[0]);
+    plan_free(pl[1]);
+    for (hipEvent_t e : ev)
+      if (e) (void)hipEventDestroy(e);
+  }
 };
 
 chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P,
@@ -31,6 +48,41 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
   if (P < 0 || (P && (!h_pairs || !h_offs)) || !h_descs || !h_n_feats)
     return fail(CHM_E_INVALID_ARG, "bad arguments");
   const int nsteps = chm_schedule_num_steps(sc);
+  // The schedule's pairs in step order: step k matches entries
+  // first[k] .. first[k+1]-1 of (sp, starts).
+  std::vector<int32_t> sp, first(nsteps + 1, 0), rows(nsteps, 1);
+  std::vector<int64_t> starts;
+  for (int k = 0; k < nsteps; ++k) {
+    const int32_t *ev, *ld, *pp;
+    int32_t nev, nld, npp;
+    chm_status st = chm_schedule_step(sc, k, &ev, &nev, &ld, &nld, &pp, &npp);
+    if (st) return st;
+    for (int i = 0; i < npp; ++i) {
+      const int p = pp[i];
+      if (p < 0 || p >= P) return fail(CHM_E_INVALID_ARG, "schedule names pair %d of %d", p, P);
+      sp.push_back(h_pairs[2 * p]);
+      sp.push_back(h_pairs[2 * p + 1]);
+      starts.push_back(h_offs[p]);
+      rows[k] = std::max(rows[k], h_n_feats[h_pairs[2 * p]]);
+    }
+    first[k + 1] = (int32_t)starts.size();
+  }
+  const int32_t total = first[nsteps];
+  hipStream_t s = (hipStream_t)stream;
+  if (sao && total > 0) {
+    const int32_t n_max = *std::max_element(rows.begin(), rows.end());
+    if (sao->work_bytes < sao_work_bytes(total, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
+    const hipError_t e = sao_upload(total, sp.data(), sao->d_kp, h_n_feats, starts.data(), sao->d_work, s);
+    if (e != hipSuccess) return fail(CHM_E_HIP, "SAO pair table upload failed: %s", hipGetErrorString(e));
+  }
+  // The host runs one step ahead of the device: while step k runs, it queues
+  // step k+1 (evictions are host bookkeeping; the stream orders a reused
+  // slot's new copy after the kernels that read its old image), then waits
+  // for step k's end before it frees step k's plan.
+  InFlight fl(s);
+  for (int i = 0; i < 2; ++i)
+    if (hipEventCreateWithFlags(&fl.ev[i], hipEventDisableTiming) != hipSuccess)
+      return fail(CHM_E_HIP, "event creation failed");
   for (int k = 0; k < nsteps; ++k) {
     const int32_t *ev, *ld, *pp;
     int32_t nev, nld, npp;
@@ -51,29 +103,27 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
     }
     st = chm_store_load(S, (int32_t)ids.size(), ids.data(), ds.data(), nf.data(), 0, stream);
     if (st) return st;
-    std::vector<int32_t> sp;
-    std::vector<int64_t> starts;
-    for (int i = 0; i < npp; ++i) {
-      const int p = pp[i];
-      if (p < 0 || p >= P) return fail(CHM_E_INVALID_ARG, "schedule names pair %d of %d", p, P);
-      sp.push_back(h_pairs[2 * p]);
-      sp.push_back(h_pairs[2 * p + 1]);
-      starts.push_back(h_offs[p]);
-    }
-    chm_plan* pl = nullptr;
-    st = plan_build(S, sp.data(), npp, starts.data(), d_out, nullptr, CHM_MATCH_BATCHED, stream, &pl);
+    const int cur = k & 1;
+    const int32_t f = first[k], n = first[k + 1] - first[k];
+    st = plan_build(S, sp.data() + 2 * (size_t)f, n, starts.data() + f, d_out, nullptr, CHM_MATCH_BATCHED,
+                    stream, &fl.pl[cur], false);
     if (st) return st;
-    st = chm_plan_execute(pl, stream);
-    chm_plan_destroy(pl);
+    st = chm_plan_execute(fl.pl[cur], stream);
     if (st) return st;
-    if (sao && npp > 0) {
-      const hipError_t e = launch_sao(npp, sp.data(), sao->d_kp, h_n_feats, starts.data(), d_out, sao->nn,
-                                      sao->num, sao->den, sao->d_filtered, nullptr, sao->d_work, false,
-                                      (hipStream_t)stream);
+    if (sao && n > 0) {
+      const hipError_t e = sao_run(f, n, total, rows[k], d_out, sao->nn, sao->num, sao->den, sao->d_filtered,
+                                   nullptr, sao->d_work, s);
       if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
     }
+    if (hipEventRecord(fl.ev[cur], s) != hipSuccess) return fail(CHM_E_HIP, "event record failed");
+    if (fl.pl[cur ^ 1]) {
+      const hipError_t e = hipEventSynchronize(fl.ev[cur ^ 1]);
+      if (e != hipSuccess) return fail(CHM_E_HIP, "schedule step %d failed: %s", k - 1, hipGetErrorString(e));
+      plan_free(fl.pl[cur ^ 1]);
+      fl.pl[cur ^ 1] = nullptr;
+    }
   }
-  hipError_t e = hipStreamSynchronize((hipStream_t)stream);
+  hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHM_E_HIP, "schedule run failed: %s", hipGetErrorString(e));
   return CHM_OK;
 }
@@ -112,7 +162,7 @@ extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc,
   if (work_bytes < sao_work_bytes(P, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
   const hipError_t e = launch_fill_u32(static_cast<uint32_t*>(d_work), 0u, 1, (hipStream_t)stream);
   if (e != hipSuccess) return fail(CHM_E_HIP, "%s", hipGetErrorString(e));
-  const SaoStep sao{d_kp, n_neighbors, score_num, score_den, d_filtered, d_work};
+  const SaoStep sao{d_kp, n_neighbors, score_num, score_den, d_filtered, d_work, work_bytes};
   return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao);
 }
 

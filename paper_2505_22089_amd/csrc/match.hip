@@ -51,6 +51,7 @@ typedef __attribute__((address_space(1))) const v4u gcv4u;
 typedef __attribute__((address_space(1))) const uint32_t gcu32;
 typedef __attribute__((address_space(1))) const uint8_t gcu8;
 typedef __attribute__((address_space(1))) const int32_t gci32;
+typedef __attribute__((address_space(3))) const int32_t lds_ci32;
 
 // popcount(x) + acc in one instruction
 __device__ __forceinline__ uint32_t bcnt_acc(uint32_t x, uint32_t acc) {
@@ -139,9 +140,9 @@ __device__ __forceinline__ uint32_t lane_read(uint32_t v, int src_lane) {
 // Called by all 64 lanes of the wavefront (the re-rank is cooperative);
 // a lane with valid false owns no query (q is any valid index) and writes
 // nothing.
-template <int KT, bool LDSC>
+template <int KT, bool LDSC, typename OffPtr>
 __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P, int q, bool valid,
-                                            const int32_t* offs) {
+                                            OffPtr offs) {
   const uint4 qc = ldg4(P.q.codes + q);
   uint32_t qb0 = 0, qb1 = 0;  // bucket ids of the query, one byte per table
   for (int t = 0; t < a.L; ++t) {
@@ -419,34 +420,37 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
   if (valid) a.out[o] = result;
 }
 
-// LDS of the per-item query sort: order (u16), walk length (u8), histogram.
+// LDS of the per-item query sort: order (u16 per query) and histogram.
 struct SortLds {
   uint16_t* order;
-  uint8_t* len;
   uint32_t* hist;
 };
 
-// Orders the item's queries by their walk length (aligned blocks over the
-// L buckets, clamped to 255), longest first, so that the 64 lanes of a
-// wavefront walk about as many blocks each.  Equal lengths come in any
-// order: every query's result is independent of who computes it and when.
-template <int WG>
+// Sort key of a query: 255 less its walk length (aligned blocks over the L
+// buckets, clamped to 255), so that ascending keys are longest walks first.
+template <typename OffPtr>
+__device__ __forceinline__ int walk_key(const MatchArgs& a, const PairDev& P, int q, OffPtr offs) {
+  const int stride = a.nb + 1;
+  int len = 0;
+  for (int t = 0; t < a.L; ++t) {
+    const int b = *(gcu8*)(P.q.ids + (size_t)t * P.q.n_pad + q);
+    len += (offs[t * stride + b + 1] - offs[t * stride + b]) >> 3;
+  }
+  return 255 - min(len, 255);
+}
+
+// Orders the item's queries by their walk length, longest first, so that
+// the 64 lanes of a wavefront walk about as many blocks each (a counting
+// sort; the key is computed again for the scatter rather than stored).
+// Equal lengths come in any order: every query's result is independent of
+// who computes it and when.
+template <int WG, typename OffPtr>
 __device__ __forceinline__ void sort_item(const MatchArgs& a, const PairDev& P, const WorkItem& w,
-                                          const int32_t* offs, const SortLds& s) {
-  const int nq = w.q1 - w.q0, stride = a.nb + 1;
+                                          OffPtr offs, const SortLds& s) {
+  const int nq = w.q1 - w.q0;
   for (int i = threadIdx.x; i < 256; i += WG) s.hist[i] = 0;
   __syncthreads();
-  for (int i = threadIdx.x; i < nq; i += WG) {
-    const int q = w.q0 + i;
-    int len = 0;
-    for (int t = 0; t < a.L; ++t) {
-      const int b = *(gcu8*)(P.q.ids + (size_t)t * P.q.n_pad + q);
-      len += (offs[t * stride + b + 1] - offs[t * stride + b]) >> 3;
-    }
-    len = 255 - min(len, 255);  // descending walk length
-    s.len[i] = (uint8_t)len;
-    atomicAdd(&s.hist[len], 1u);
-  }
+  for (int i = threadIdx.x; i < nq; i += WG) atomicAdd(&s.hist[walk_key(a, P, w.q0 + i, offs)], 1u);
   __syncthreads();
   if (threadIdx.x < 64) {  // exclusive scan, 4 bins per lane
     const int lane = threadIdx.x;
@@ -470,14 +474,14 @@ __device__ __forceinline__ void sort_item(const MatchArgs& a, const PairDev& P, 
     }
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < nq; i += WG) s.order[atomicAdd(&s.hist[s.len[i]], 1u)] = (uint16_t)i;
+  for (int i = threadIdx.x; i < nq; i += WG)
+    s.order[atomicAdd(&s.hist[walk_key(a, P, w.q0 + i, offs)], 1u)] = (uint16_t)i;
   __syncthreads();
 }
 
-template <int KT, bool LDSC, int WG>
+template <int KT, bool LDSC, int WG, typename OffPtr>
 __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, const WorkItem& w,
-                                         const int32_t* offs, int* s_chunk, const SortLds& s) {
-  const bool sorted = w.q1 - w.q0 <= kSortMax;
+                                         OffPtr offs, int* s_chunk, const SortLds& s, bool sorted) {
   if (sorted) sort_item<WG>(a, P, w, offs, s);
   // Wavefronts take 64-query chunks of the item in turn.
   const int lane = __lane_id();
@@ -495,21 +499,22 @@ __device__ __forceinline__ void run_item(const MatchArgs& a, const PairDev& P, c
 
 template <int KT, int WG, bool LDSC, bool PERSIST>
 __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
-  // All LDS is dynamic and the codes come first, at LDS address 0, so a
-  // code's LDS address is its member value (16 j) itself.
+  // All LDS is dynamic: the staged codes from address 0, so a code's LDS
+  // address is its member value (16 j) itself; the control words and the
+  // sort histogram at the top; an item's sort order just below them.
   extern __shared__ uint4 smem[];
+  char* lds = reinterpret_cast<char*>(smem);
+  const int top = LDSC ? a.lds_top : 2 * kSortMax;
   const int ncodes = LDSC ? a.lds_max_feats : 0;
-  const int noffs = LDSC ? a.L * (a.nb + 1) : 0;
-  uint4* sCodes = smem;
-  int32_t* sOffs = reinterpret_cast<int32_t*>(smem + ncodes);
-  int* sCtl = reinterpret_cast<int*>(smem + ncodes + (noffs + 3) / 4);
+  const int offs_bytes = (a.L * (a.nb + 1) * 4 + 15) & ~15;
+  int* sCtl = reinterpret_cast<int*>(lds + top);
   int& s_item = sCtl[0];
   int& s_chunk = sCtl[1];
   SortLds sl;
   sl.hist = reinterpret_cast<uint32_t*>(sCtl + 4);
-  sl.order = reinterpret_cast<uint16_t*>(sl.hist + 256);
-  sl.len = reinterpret_cast<uint8_t*>(sl.order + kSortMax);
   const uint4* staged = nullptr;
+  int stage_end = 0;        // bytes of LDS the current stage occupies
+  bool staged_offs = false;  // whether they include the bucket offsets
   int it = PERSIST ? 0 : a.item_base + (int)blockIdx.x;
   // Persistent: start with the bin of this work-group's XCD (work-groups
   // are dealt to the XCDs round-robin), then help the other bins in turn.
@@ -544,28 +549,40 @@ __global__ __launch_bounds__(WG) void k_match(MatchArgs a) {
     const PairDev& P = a.pairs[w.pair];
     const bool use_lds = LDSC && P.d.n <= ncodes;
     if (use_lds && staged != P.d.codes) {
-      for (int j = threadIdx.x; j < P.d.n; j += WG) sCodes[j] = ldg4(P.d.codes + j);
-      for (int i = threadIdx.x; i < a.L * (a.nb + 1); i += WG) sOffs[i] = *(gci32*)(P.d.offsets + i);
+      // the offsets join the stage when a full-size sort still fits above it
+      const int code_bytes = 16 * P.d.n;
+      staged_offs = code_bytes + offs_bytes + 2 * kSortMax <= top;
+      stage_end = code_bytes + (staged_offs ? offs_bytes : 0);
+      for (int j = threadIdx.x; j < P.d.n; j += WG) smem[j] = ldg4(P.d.codes + j);
+      if (staged_offs) {
+        int32_t* so = reinterpret_cast<int32_t*>(lds + code_bytes);
+        for (int i = threadIdx.x; i < a.L * (a.nb + 1); i += WG) so[i] = *(gci32*)(P.d.offsets + i);
+      }
       staged = P.d.codes;
     }
+    const int nq = w.q1 - w.q0;
+    const bool sorted = nq <= kSortMax && top - 2 * nq >= (use_lds ? stage_end : 0);
+    if (sorted && !use_lds && top - 2 * nq < stage_end) staged = nullptr;  // the order overwrites the stage
+    sl.order = reinterpret_cast<uint16_t*>(lds + top - 2 * (sorted ? nq : 0));
     __syncthreads();
-    if (use_lds)
-      run_item<KT, true, WG>(a, P, w, sOffs, &s_chunk, sl);
+    // The offsets pointer carries its address space in its type, so each
+    // walk reads them with LDS or global loads, not flat ones.
+    gci32* goffs = (gci32*)P.d.offsets;
+    if (use_lds && staged_offs)
+      run_item<KT, true, WG>(a, P, w, reinterpret_cast<lds_ci32*>((size_t)(16 * P.d.n)), &s_chunk, sl, sorted);
+    else if (use_lds)
+      run_item<KT, true, WG>(a, P, w, goffs, &s_chunk, sl, sorted);
     else
-      run_item<KT, false, WG>(a, P, w, P.d.offsets, &s_chunk, sl);
+      run_item<KT, false, WG>(a, P, w, goffs, &s_chunk, sl, sorted);
     __syncthreads();
     if (!PERSIST) break;
   }
 }
 
-size_t match_lds_bytes(int lds_max_feats, int L, int nb) {
-  const size_t offs = ((size_t)L * (nb + 1) + 3) / 4 * sizeof(uint4);
-  return (size_t)lds_max_feats * sizeof(uint4) + offs + kMatchLdsTail;
-}
 
 template <int KT, int WG, bool LDSC, bool PERSIST>
 static hipError_t launch_one(const MatchArgs& a, int grid, hipStream_t s) {
-  const size_t lds = LDSC ? match_lds_bytes(a.lds_max_feats, a.L, a.nb) : kMatchLdsTail;
+  const size_t lds = LDSC ? (size_t)a.lds_top + kLdsTop : kMatchLdsTail;
   auto fn = k_match<KT, WG, LDSC, PERSIST>;
   static int static_lds = -1;  // the code stage must start at LDS address 0
   if (static_lds < 0) {

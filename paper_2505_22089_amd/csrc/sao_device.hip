@@ -535,44 +535,58 @@ uint64_t sao_work_bytes(int32_t n_pairs, int32_t max_rows) {
          (uint64_t)B * pair_scratch_bytes(std::max(max_rows, 1));
 }
 
-hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
-                      const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match, int32_t nn,
-                      int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work, bool clear_errors,
-                      hipStream_t s) {
-  int32_t n_max = 1;
+hipError_t sao_upload(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_starts, void* d_work, hipStream_t s) {
   std::vector<SaoPair> hp((size_t)n_pairs);
   for (int32_t p = 0; p < n_pairs; ++p) {
     const int32_t q = h_pairs[2 * p], d = h_pairs[2 * p + 1];
-    hp[(size_t)p] = SaoPair{d_kp[q], d_kp[d], h_n_feats[q], h_n_feats[d], h_offs[p]};
-    n_max = std::max(n_max, h_n_feats[q]);
+    hp[(size_t)p] = SaoPair{d_kp[q], d_kp[d], h_n_feats[q], h_n_feats[d], h_starts[p]};
   }
+  SaoPair* dp = reinterpret_cast<SaoPair*>(static_cast<uint8_t*>(d_work) + 256);
+  hipError_t e = hipSuccess;
+  if (n_pairs > 0) e = hipMemcpyAsync(dp, hp.data(), sizeof(SaoPair) * hp.size(), hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);  // hp is freed on return
+  return e;
+}
+
+hipError_t sao_run(int32_t first, int32_t count, int32_t table_pairs, int32_t n_max, const int32_t* d_match,
+                   int32_t nn, int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work,
+                   hipStream_t s) {
   uint8_t* w = static_cast<uint8_t*>(d_work);
   SaoPair* dp = reinterpret_cast<SaoPair*>(w + 256);
-  hipError_t e = clear_errors ? launch_fill_u32(reinterpret_cast<uint32_t*>(w), 0u, 1, s) : hipSuccess;
-  if (e == hipSuccess) e = hipMemcpyAsync(dp, hp.data(), sizeof(SaoPair) * hp.size(), hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipStreamSynchronize(s);  // hp is freed on return
-  if (e != hipSuccess) return e;
   SaoArgs a;
-  a.n_max = n_max;
+  a.n_max = std::max(n_max, 1);
   a.match = d_match;
   a.out = d_out;
   a.ced = d_ced;
   a.nn = nn;
   a.num = num;
   a.den = den;
-  a.scratch = w + 256 + round16(sizeof(SaoPair) * (uint64_t)n_pairs);
-  a.scratch_bytes = pair_scratch_bytes(n_max);
+  a.scratch = w + 256 + round16(sizeof(SaoPair) * (uint64_t)table_pairs);
+  a.scratch_bytes = pair_scratch_bytes(a.n_max);
   a.errors = reinterpret_cast<int32_t*>(w);
-  const unsigned chunks = (unsigned)((n_max + kSaoWG - 1) / kSaoWG);
-  for (int32_t b0 = 0; b0 < n_pairs; b0 += kSaoBatch) {
-    a.pairs = dp + b0;
-    a.n_pairs = std::min(kSaoBatch, n_pairs - b0);
+  const unsigned chunks = (unsigned)((a.n_max + kSaoWG - 1) / kSaoWG);
+  for (int32_t b0 = 0; b0 < count; b0 += kSaoBatch) {
+    a.pairs = dp + first + b0;
+    a.n_pairs = std::min(kSaoBatch, count - b0);
     hipLaunchKernelGGL(k_sao_build, dim3(a.n_pairs), dim3(kSaoBuildWG), 0, s, a);
     hipLaunchKernelGGL(k_sao_search, dim3(chunks, a.n_pairs), dim3(kSaoWG), 0, s, a);
-    e = hipGetLastError();
+    const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
+}
+
+hipError_t launch_sao(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                      const int32_t* h_n_feats, const int64_t* h_offs, const int32_t* d_match, int32_t nn,
+                      int32_t num, int32_t den, int32_t* d_out, int32_t* d_ced, void* d_work, bool clear_errors,
+                      hipStream_t s) {
+  int32_t n_max = 1;
+  for (int32_t p = 0; p < n_pairs; ++p) n_max = std::max(n_max, h_n_feats[h_pairs[2 * p]]);
+  hipError_t e = clear_errors ? launch_fill_u32(static_cast<uint32_t*>(d_work), 0u, 1, s) : hipSuccess;
+  if (e == hipSuccess) e = sao_upload(n_pairs, h_pairs, d_kp, h_n_feats, h_offs, d_work, s);
+  if (e == hipSuccess) e = sao_run(0, n_pairs, n_pairs, n_max, d_match, nn, num, den, d_out, d_ced, d_work, s);
+  return e;
 }
 
 }  // namespace chm

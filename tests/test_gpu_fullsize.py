@@ -68,7 +68,7 @@ def test_strips_sampled_pairs():
     st = new_store(wl)
     load_all(st, wl.images)
     nd = np.array([x.shape[0] for x in wl.images])
-    assert nd.min() < 9341 < nd.max()  # LDS-staged and global-memory db images both occur
+    assert nd.min() < 10175 < nd.max()  # LDS-staged and global-memory db images both occur
     out, _, offs = run_match(st, wl.pairs)
     idx = sample_pairs(wl, 8, seed=3)
     ref = oracle_slices(wl, wl.pairs[idx])
@@ -121,4 +121,42 @@ def test_grid_through_binding_mbr_schedule():
     ref, roffs, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
     assert np.array_equal(offs, roffs)
     assert np.array_equal(out.cpu().numpy(), ref)
+    st.close()
+
+
+def test_db_images_around_the_lds_stage_limits():
+    """Db images on both sides of each LDS layout limit, in one persistent
+    launch and per pair: the last size whose bucket offsets are staged with
+    the codes, sizes whose items shrink so their sort order fits above the
+    stage, the largest size whose codes fit at all (its items run unsorted)
+    and the next size up (codes from HBM, in the same launch), with small db
+    images between them so work-groups re-stage, every output against the
+    oracle."""
+    # Limits of the layout on a CU with 160 KiB of LDS (L = 6, m = 8): the
+    # control words and histogram take the top 1040 bytes; codes take 16 B a
+    # point from address 0; offsets (6 x 257 int32, 6176 B) join them when a
+    # 2048-query sort order (4096 B) still fits; an item's order takes 2 B a
+    # query.  On another LDS size the same images are still valid inputs.
+    top = 160 * 1024 - 1040
+    offsets_staged = (top - 6176 - 4096) // 16        # 9533
+    sorted_1024 = (top - 2 * 1024) // 16              # 10047
+    codes = top // 16                                 # 10175
+    sizes = [offsets_staged, offsets_staged + 1, 10000, sorted_1024, sorted_1024 + 1, codes, codes + 1,
+             2000, 700]
+    n = len(sizes)
+    centres = np.stack([np.arange(n) * 0.5, np.zeros(n)], 1)
+    pairs = np.array([(q, d) for d in range(n) for q in ((d + 1) % n, (d + n - 1) % n)], np.int32)
+    wl = synth.track_workload("lds-limits", 77, centres, sizes, pairs, 0.4)
+    st = new_store(wl)
+    load_all(st, wl.images)
+    ref = oracle_slices(wl, wl.pairs)
+    for tuning in ((2048, 1024, 1, 1), (512, 1024, 1, 1), (1536, 1024, 1, 1)):
+        st.set_tuning(*tuning)
+        out, _, offs = run_match(st, wl.pairs)
+        for p in range(len(wl.pairs)):
+            assert np.array_equal(out[offs[p]:offs[p + 1]], ref[p]), (tuning, p, wl.pairs[p])
+    st.set_tuning(wg_threads=1024, lds_codes=1)
+    out, _, offs = run_match(st, wl.pairs, mode=chm.MATCH_PLAIN)
+    for p in range(len(wl.pairs)):
+        assert np.array_equal(out[offs[p]:offs[p + 1]], ref[p]), ("plain", p)
     st.close()
