@@ -295,12 +295,16 @@ chm_status chm_gps_order(int32_t n, const int32_t *edges, int32_t n_edges, const
  * step, evicts, loads the new images from host memory (h_descs[image],
  * h_n_feats[image]; pinned memory makes the copies DMA transfers), builds
  * their codes and tables, and matches the step's pairs in one batched launch.
- * Copies and kernels all go on `stream`, in order; the host queues step k+1
- * while the device runs step k, and the call returns when the stream has
- * finished the last step.  Host buffers must stay valid until then.
- * Outputs as in chm_plan_create for the schedule's pair list.  The store's
- * arena must hold cap_bytes of images plus two steps' work lists (tens of
- * bytes per work item). */
+ * Kernels go on `stream`; descriptor copies go on a second stream the call
+ * creates, so step k+1's copies overlap step k's matching when the arena has
+ * room for them beside what step k still reads (slots evicted at step k+1
+ * are held until step k ends; when room runs short the call waits for that
+ * and frees them first).  Work queued on `stream` before the call finishes
+ * before any copy starts.  The call returns when both streams are done; host
+ * buffers must stay valid until then.  Outputs as in chm_plan_create for the
+ * schedule's pair list.  The store's arena must hold cap_bytes of images plus
+ * a step's work list (tens of bytes per work item); what it holds beyond
+ * that is used to copy ahead. */
 chm_status chm_run_schedule(chm_store *store, const chm_schedule *s, const int32_t *h_pairs,
                             int32_t n_pairs, const void *const *h_descs,
                             const int32_t *h_n_feats, const int64_t *h_out_offsets,

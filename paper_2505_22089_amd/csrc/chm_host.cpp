@@ -291,10 +291,8 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
   return CHM_OK;
 }
 
-extern "C" chm_status chm_store_load(chm_store* S, int32_t count, const int32_t* ids,
-                                     const void* const* descs, const int32_t* n_feats,
-                                     int32_t on_device, void* stream) {
-  clear_error();
+chm_status chm::load_check(const chm_store* S, int32_t count, const int32_t* ids, const void* const* descs,
+                           const int32_t* n_feats) {
   if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
   if (count < 0) return fail(CHM_E_INVALID_ARG, "count < 0");
   if (count == 0) return CHM_OK;
@@ -308,37 +306,68 @@ extern "C" chm_status chm_store_load(chm_store* S, int32_t count, const int32_t*
       return fail(CHM_E_INVALID_ARG, "image %d: n_feats %d outside 0..%d", ids[i], n_feats[i], CHM_MAX_FEATS);
     if (n_feats[i] > 0 && !descs[i]) return fail(CHM_E_INVALID_ARG, "image %d: descriptors NULL", ids[i]);
   }
-  std::vector<ImageSlot> slots(count);
+  return CHM_OK;
+}
+
+chm_status chm::load_alloc(chm_store* S, int32_t count, const int32_t* ids, const int32_t* n_feats,
+                           std::vector<ImageSlot>* slots) {
+  slots->assign((size_t)count, ImageSlot());
   for (int i = 0; i < count; ++i) {
     const ImageLayout l = image_layout(S->cfg.num_tables, S->cfg.bucket_bits, n_feats[i]);
-    slots[i].n = n_feats[i];
-    slots[i].bytes = l.total;
-    if (!S->arena.alloc(l.total, &slots[i].off)) {
-      for (int k = 0; k < i; ++k) S->arena.release(slots[k].off, slots[k].bytes);
+    ImageSlot& sl = (*slots)[(size_t)i];
+    sl.n = n_feats[i];
+    sl.bytes = l.total;
+    if (!S->arena.alloc(l.total, &sl.off)) {
+      for (int k = 0; k < i; ++k) S->arena.release((*slots)[(size_t)k].off, (*slots)[(size_t)k].bytes);
+      slots->clear();
       return fail(CHM_E_CAPACITY, "arena cannot hold image %d (%llu bytes)", ids[i],
                   (unsigned long long)l.total);
     }
   }
-  hipStream_t s = (hipStream_t)stream;
+  return CHM_OK;
+}
+
+chm_status chm::load_commit(chm_store* S, int32_t count, const int32_t* ids, const void* const* descs,
+                            std::vector<ImageSlot>& slots, bool on_device, hipStream_t s,
+                            std::vector<const ImageSlot*>* ptrs) {
   const hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  std::vector<const ImageSlot*> ptrs;
   for (int i = 0; i < count; ++i) {
-    if (slots[i].n > 0) {
-      hipError_t e = hipMemcpyAsync(S->base + slots[i].off, descs[i], (size_t)slots[i].n * kDim, kind, s);
+    if (slots[(size_t)i].n > 0) {
+      hipError_t e = hipMemcpyAsync(S->base + slots[(size_t)i].off, descs[i], (size_t)slots[(size_t)i].n * kDim,
+                                    kind, s);
       if (e != hipSuccess) {
-        for (int k = 0; k < count; ++k) S->arena.release(slots[k].off, slots[k].bytes);
+        (void)hipStreamSynchronize(s);
+        for (int k = 0; k < count; ++k) S->arena.release(slots[(size_t)k].off, slots[(size_t)k].bytes);
         return fail(CHM_E_HIP, "descriptor copy failed: %s", hipGetErrorString(e));
       }
     }
-    slots[i].gen = ++S->gen_counter;
-    auto& ref = S->images[ids[i]] = slots[i];
-    ptrs.push_back(&ref);
-    S->stats.resident_bytes += slots[i].bytes;
-    (on_device ? S->stats.d2d_bytes : S->stats.h2d_bytes) += (uint64_t)slots[i].n * kDim;
+  }
+  for (int i = 0; i < count; ++i) {
+    slots[(size_t)i].gen = ++S->gen_counter;
+    auto& ref = S->images[ids[i]] = slots[(size_t)i];
+    ptrs->push_back(&ref);
+    S->stats.resident_bytes += ref.bytes;
+    (on_device ? S->stats.d2d_bytes : S->stats.h2d_bytes) += (uint64_t)ref.n * kDim;
     S->stats.images_loaded += 1;
   }
   S->stats.resident_images = (int32_t)S->images.size();
   S->stats.resident_peak = std::max(S->stats.resident_peak, S->stats.resident_bytes);
+  return CHM_OK;
+}
+
+extern "C" chm_status chm_store_load(chm_store* S, int32_t count, const int32_t* ids,
+                                     const void* const* descs, const int32_t* n_feats,
+                                     int32_t on_device, void* stream) {
+  clear_error();
+  chm_status st = load_check(S, count, ids, descs, n_feats);
+  if (st || count == 0) return st;
+  std::vector<ImageSlot> slots;
+  st = load_alloc(S, count, ids, n_feats, &slots);
+  if (st) return st;
+  hipStream_t s = (hipStream_t)stream;
+  std::vector<const ImageSlot*> ptrs;
+  st = load_commit(S, count, ids, descs, slots, on_device != 0, s, &ptrs);
+  if (st) return st;
   return hash_images(S, ptrs, s);
 }
 
@@ -355,8 +384,8 @@ extern "C" chm_status chm_store_rehash(chm_store* S, int32_t count, const int32_
   return hash_images(S, ptrs, (hipStream_t)stream);
 }
 
-extern "C" chm_status chm_store_evict(chm_store* S, int32_t count, const int32_t* ids) {
-  clear_error();
+chm_status chm::evict_hold(chm_store* S, int32_t count, const int32_t* ids,
+                           std::vector<std::pair<uint64_t, uint64_t>>* held) {
   if (!S) return fail(CHM_E_INVALID_ARG, "store is NULL");
   if (count < 0 || (count > 0 && !ids)) return fail(CHM_E_INVALID_ARG, "bad image list");
   for (int i = 0; i < count; ++i)
@@ -364,13 +393,26 @@ extern "C" chm_status chm_store_evict(chm_store* S, int32_t count, const int32_t
   for (int i = 0; i < count; ++i) {
     auto it = S->images.find(ids[i]);
     if (it == S->images.end()) continue;  // listed twice
-    S->arena.release(it->second.off, it->second.bytes);
+    if (held)
+      held->push_back({it->second.off, it->second.bytes});
+    else
+      S->arena.release(it->second.off, it->second.bytes);
     S->stats.resident_bytes -= it->second.bytes;
     S->stats.images_evicted += 1;
     S->images.erase(it);
   }
   S->stats.resident_images = (int32_t)S->images.size();
   return CHM_OK;
+}
+
+void chm::release_held(chm_store* S, std::vector<std::pair<uint64_t, uint64_t>>* held) {
+  for (auto& h : *held) S->arena.release(h.first, h.second);
+  held->clear();
+}
+
+extern "C" chm_status chm_store_evict(chm_store* S, int32_t count, const int32_t* ids) {
+  clear_error();
+  return evict_hold(S, count, ids, nullptr);
 }
 
 extern "C" chm_status chm_store_image_feats(const chm_store* S, int32_t id, int32_t* out) {

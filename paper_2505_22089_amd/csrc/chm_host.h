@@ -103,4 +103,20 @@ chm_status plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int
                       bool wait_upload = true);
 // Releases a plan without waiting: the caller has seen its work finish.
 void plan_free(chm_plan* pl);
+// chm_store_load in parts: argument checks; arena slots for all images or
+// none (CHM_E_CAPACITY, nothing changed); descriptor copies queued on `s`
+// and the images registered as resident (their codes and tables are built
+// by hash_images on whichever stream has waited for the copies).
+chm_status load_check(const chm_store* S, int32_t count, const int32_t* ids, const void* const* descs,
+                      const int32_t* n_feats);
+chm_status load_alloc(chm_store* S, int32_t count, const int32_t* ids, const int32_t* n_feats,
+                      std::vector<ImageSlot>* slots);
+chm_status load_commit(chm_store* S, int32_t count, const int32_t* ids, const void* const* descs,
+                       std::vector<ImageSlot>& slots, bool on_device, hipStream_t s,
+                       std::vector<const ImageSlot*>* ptrs);
+// chm_store_evict that, with `held`, hands the slots (offset, bytes) to the
+// caller instead of freeing them: queued kernels may still read them.
+chm_status evict_hold(chm_store* S, int32_t count, const int32_t* ids,
+                      std::vector<std::pair<uint64_t, uint64_t>>* held);
+void release_held(chm_store* S, std::vector<std::pair<uint64_t, uint64_t>>* held);
 }  // namespace chm

@@ -7,6 +7,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <string>
 #include <vector>
 
 #include "chm.h"
@@ -25,19 +26,28 @@ struct SaoStep {
   uint64_t work_bytes;
 };
 
-// Plans still read by queued work, and the events that mark their ends.  On
-// the way out (normal or not) the stream is drained before anything is freed.
+// What queued work may still read: the plans of the last two steps and the
+// slots evicted at them, with the events that mark each step's end on the
+// compute stream; and the copy stream with its per-step events.  On the way
+// out (normal or not) both streams are drained before anything is freed.
+using Held = std::vector<std::pair<uint64_t, uint64_t>>;
 struct InFlight {
-  hipStream_t s;
-  hipEvent_t ev[2] = {nullptr, nullptr};
+  chm_store* S;
+  hipStream_t s, xs = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr}, cev[2] = {nullptr, nullptr};
   chm_plan* pl[2] = {nullptr, nullptr};
-  explicit InFlight(hipStream_t st) : s(st) {}
+  Held held[2];
+  InFlight(chm_store* st, hipStream_t cs) : S(st), s(cs) {}
   ~InFlight() {
-    if (pl[0] || pl[1]) (void)hipStreamSynchronize(s);
-    plan_free(pl[0]);
-    plan_free(pl[1]);
-    for (hipEvent_t e : ev)
+    (void)hipStreamSynchronize(s);
+    if (xs) (void)hipStreamSynchronize(xs);
+    for (int i = 0; i < 2; ++i) {
+      plan_free(pl[i]);
+      release_held(S, &held[i]);
+    }
+    for (hipEvent_t e : {ev[0], ev[1], cev[0], cev[1]})
       if (e) (void)hipEventDestroy(e);
+    if (xs) (void)hipStreamDestroy(xs);
   }
 };
 
@@ -75,15 +85,42 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
     const hipError_t e = sao_upload(total, sp.data(), sao->d_kp, h_n_feats, starts.data(), sao->d_work, s);
     if (e != hipSuccess) return fail(CHM_E_HIP, "SAO pair table upload failed: %s", hipGetErrorString(e));
   }
-  // The host runs one step ahead of the device: while step k runs, it queues
-  // step k+1 (evictions are host bookkeeping; the stream orders a reused
-  // slot's new copy after the kernels that read its old image), then waits
-  // for step k's end before it frees step k's plan.
-  InFlight fl(s);
-  for (int i = 0; i < 2; ++i)
-    if (hipEventCreateWithFlags(&fl.ev[i], hipEventDisableTiming) != hipSuccess)
+  // Two streams: descriptor copies on xs, everything else on the caller's
+  // stream s.  The host queues step k+1 while the device runs step k:
+  // - step k+1's images are copied on xs into arena memory that no queued
+  //   kernel reads: memory that was free when the call began (xs first waits
+  //   for s, so work queued before the call is done), or released once the
+  //   host has seen the step that last read it end;
+  // - the slots evicted at step k+1 were last read by step k, so they are
+  //   held until step k's end event; when the arena has no other room for
+  //   step k+1's images, the host waits for that event and frees them first;
+  // - s waits for step k+1's copies before it hashes the new images.
+  InFlight fl(S, s);
+  if (hipStreamCreateWithFlags(&fl.xs, hipStreamNonBlocking) != hipSuccess)
+    return fail(CHM_E_HIP, "stream creation failed");
+  for (hipEvent_t* e : {&fl.ev[0], &fl.ev[1], &fl.cev[0], &fl.cev[1]})
+    if (hipEventCreateWithFlags(e, hipEventDisableTiming) != hipSuccess)
       return fail(CHM_E_HIP, "event creation failed");
+  if (hipEventRecord(fl.cev[1], s) != hipSuccess || hipStreamWaitEvent(fl.xs, fl.cev[1], 0) != hipSuccess)
+    return fail(CHM_E_HIP, "stream ordering failed");
   for (int k = 0; k < nsteps; ++k) {
+    const int cur = k & 1;
+    // When the arena has no room left for step k, wait for step k-1's end
+    // and free its plan and the slots evicted at step k: the state in which
+    // a driver without look-ahead would allocate.  CHM_E_CAPACITY when
+    // nothing is left to free.
+    auto make_room = [&]() -> chm_status {
+      if (fl.held[cur].empty() && !fl.pl[cur ^ 1]) return CHM_E_CAPACITY;
+      if (k > 0) {
+        const hipError_t e = hipEventSynchronize(fl.ev[cur ^ 1]);
+        if (e != hipSuccess) return fail(CHM_E_HIP, "schedule step %d failed: %s", k - 1, hipGetErrorString(e));
+      }
+      plan_free(fl.pl[cur ^ 1]);
+      fl.pl[cur ^ 1] = nullptr;
+      release_held(S, &fl.held[cur]);
+      clear_error();
+      return CHM_OK;
+    };
     const int32_t *ev, *ld, *pp;
     int32_t nev, nld, npp;
     chm_status st = chm_schedule_step(sc, k, &ev, &nev, &ld, &nld, &pp, &npp);
@@ -91,7 +128,7 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
     std::vector<int32_t> evict;
     for (int i = 0; i < nev; ++i)
       if (S->images.count(ev[i])) evict.push_back(ev[i]);
-    st = chm_store_evict(S, (int32_t)evict.size(), evict.data());
+    st = evict_hold(S, (int32_t)evict.size(), evict.data(), &fl.held[cur]);
     if (st) return st;
     std::vector<int32_t> ids, nf;
     std::vector<const void*> ds;
@@ -101,12 +138,39 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
       ds.push_back(h_descs[ld[i]]);
       nf.push_back(h_n_feats[ld[i]]);
     }
-    st = chm_store_load(S, (int32_t)ids.size(), ids.data(), ds.data(), nf.data(), 0, stream);
-    if (st) return st;
-    const int cur = k & 1;
+    const int32_t nl = (int32_t)ids.size();
+    if (nl > 0) {
+      st = load_check(S, nl, ids.data(), ds.data(), nf.data());
+      if (st) return st;
+      std::vector<ImageSlot> slots;
+      st = load_alloc(S, nl, ids.data(), nf.data(), &slots);
+      if (st == CHM_E_CAPACITY) {
+        const std::string why = chm_last_error();
+        const chm_status r = make_room();
+        if (r == CHM_E_CAPACITY) return fail(CHM_E_CAPACITY, "%s", why.c_str());
+        if (r) return r;
+        st = load_alloc(S, nl, ids.data(), nf.data(), &slots);
+      }
+      if (st) return st;
+      std::vector<const ImageSlot*> ptrs;
+      st = load_commit(S, nl, ids.data(), ds.data(), slots, false, fl.xs, &ptrs);
+      if (st) return st;
+      if (hipEventRecord(fl.cev[cur], fl.xs) != hipSuccess || hipStreamWaitEvent(s, fl.cev[cur], 0) != hipSuccess)
+        return fail(CHM_E_HIP, "stream ordering failed");
+      st = hash_images(S, ptrs, s);
+      if (st) return st;
+    }
     const int32_t f = first[k], n = first[k + 1] - first[k];
     st = plan_build(S, sp.data() + 2 * (size_t)f, n, starts.data() + f, d_out, nullptr, CHM_MATCH_BATCHED,
                     stream, &fl.pl[cur], false);
+    if (st == CHM_E_CAPACITY) {
+      const std::string why = chm_last_error();
+      const chm_status r = make_room();
+      if (r == CHM_E_CAPACITY) return fail(CHM_E_CAPACITY, "%s", why.c_str());
+      if (r) return r;
+      st = plan_build(S, sp.data() + 2 * (size_t)f, n, starts.data() + f, d_out, nullptr, CHM_MATCH_BATCHED,
+                      stream, &fl.pl[cur], false);
+    }
     if (st) return st;
     st = chm_plan_execute(fl.pl[cur], stream);
     if (st) return st;
@@ -116,12 +180,16 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
       if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
     }
     if (hipEventRecord(fl.ev[cur], s) != hipSuccess) return fail(CHM_E_HIP, "event record failed");
-    if (fl.pl[cur ^ 1]) {
+    // Step k-1 has ended: its plan and the slots evicted at step k (last
+    // read by step k-1) are free.
+    if (k > 0) {
       const hipError_t e = hipEventSynchronize(fl.ev[cur ^ 1]);
       if (e != hipSuccess) return fail(CHM_E_HIP, "schedule step %d failed: %s", k - 1, hipGetErrorString(e));
       plan_free(fl.pl[cur ^ 1]);
       fl.pl[cur ^ 1] = nullptr;
+      release_held(S, &fl.held[cur ^ 1]);
     }
+    release_held(S, &fl.held[cur]);
   }
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHM_E_HIP, "schedule run failed: %s", hipGetErrorString(e));

@@ -100,7 +100,13 @@ def test_knn_200x40000_sampled_pairs():
     st32.close()
 
 
-def test_grid_through_binding_mbr_schedule():
+@pytest.mark.parametrize("slack_caps", [0, 0.03, 0.1, 1])
+def test_grid_through_binding_mbr_schedule(slack_caps):
+    """slack_caps = 0: the arena holds little beyond the cap, so most block
+    rows free the previous row's evictions before copying (after its end);
+    small slacks: copies run ahead until the arena is short of room for a
+    row's images or its plan; 1: room for a whole second cap, so copies run
+    ahead on the copy stream."""
     wl = synth.config5(rows=8, cols=30, n_feats=2000)
     n = len(wl.images)
     cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio)
@@ -108,13 +114,14 @@ def test_grid_through_binding_mbr_schedule():
     cap = 40 * sizes[0]  # 40 of 240 images resident at a time
     sched = chm.schedule_mbr(n, wl.pairs, sizes, cap, 16, keep_handle=True)
     assert sched.iterations >= 2 and max(len(s["load"]) for s in sched.steps) > 0
-    arena = torch.empty(chm.store_overhead_bytes(cfg) + cap + (16 << 20), dtype=torch.uint8,
-                        device=device())
+    arena = torch.empty(chm.store_overhead_bytes(cfg) + int((1 + slack_caps) * cap) + (4 << 20),
+                        dtype=torch.uint8, device=device())
     st = chm.Store(cfg, wl.W, wl.mu, arena)
     offs = np.zeros(len(wl.pairs) + 1, np.int64)
     offs[1:] = np.cumsum([wl.images[q].shape[0] for q in wl.pairs[:, 0]])
     out = torch.full((int(offs[-1]),), -7, dtype=torch.int32, device=device())
     chm.run_schedule(st, sched, wl.pairs, wl.images, offs, out)
+    assert st.stats().images_loaded == sum(len(x["load"]) for x in sched.steps)
     torch.cuda.synchronize()
     chm.schedule_free(sched)
     H = O.hash_workload(wl)
