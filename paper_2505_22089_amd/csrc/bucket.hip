@@ -5,12 +5,13 @@
 // A member is stored as 16 j, the byte offset of db point j's long code, so
 // a matching lane addresses the code with no arithmetic.  Images too large
 // for the match kernel's LDS code stage also get their codes copied in
-// bucket order, so that the 8 codes of a block are one contiguous 128 bytes.  Each bucket's range
-// of the members array is padded to a multiple of 8 entries with copies of
-// the bucket's first (smallest) member, and starts at a multiple of 8: a
-// matching lane then reads whole aligned 32-byte blocks of 8 members and
-// needs no bounds test per entry (a repeated member is a candidate already
-// seen, which the set semantics of the candidate list drop).
+// bucket order, so that the 8 codes of a block are one contiguous 128
+// bytes.  Each bucket's range of the members array is padded to a multiple
+// of 8 entries with copies of the bucket's first (smallest) member, and
+// starts at a multiple of 8: a matching lane then reads whole aligned
+// 32-byte blocks of 8 members and needs no bounds test per entry (a repeated
+// member is a candidate already seen, which the set semantics of the
+// candidate list drop).
 // offsets[t][b] .. offsets[t][b + 1] is the padded range.
 //
 // One work-group per (image, table).  The table's ids are staged in LDS once;

@@ -327,15 +327,22 @@ __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
   if (lane == 0) pc.fixflips[wid] = flips;
 }
 
-// Sums the batch's fix-up count (the region counts) and changed bits (the
-// k_fixup slots) into the store's running counters.
+// Adds the batch's fix-up count (the region counts) and changed bits (the
+// k_fixup slots) to the store's running counters: the entries are spread
+// over the whole grid, each work-group sums its share in LDS and adds it
+// with one atomic per counter.
 __device__ void fix_count(const ProjConsts& pc, int n_fix_waves) {
   __shared__ unsigned long long s_sum[2];
   if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
   __syncthreads();
   unsigned long long a = 0, b = 0;
-  for (int i = threadIdx.x; i < pc.n_waves; i += blockDim.x) a += pc.fixlist[1 + i];
-  for (int i = threadIdx.x; i < n_fix_waves; i += blockDim.x) b += pc.fixflips[i];
+  const int n = pc.n_waves + n_fix_waves;
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    if (i < pc.n_waves)
+      a += pc.fixlist[1 + i];
+    else
+      b += pc.fixflips[i - pc.n_waves];
+  }
   if (a) atomicAdd(&s_sum[0], a);
   if (b) atomicAdd(&s_sum[1], b);
   __syncthreads();
@@ -345,12 +352,12 @@ __device__ void fix_count(const ProjConsts& pc, int n_fix_waves) {
   }
 }
 
-// Without an overflow of the fix-up list, work-group 0 only counts.  After
-// one, every work-group rebuilds its share of the codes and bucket ids of
-// the batch from exact values (adversarial inputs only).
+// Without an overflow of the fix-up list, the work-groups only count.
+// After one, every work-group rebuilds its share of the codes and bucket ids
+// of the batch from exact values (adversarial inputs only).
 __global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc, int n_fix_waves) {
   if (pc.fixlist[0] == 0) {
-    if (blockIdx.x == 0) fix_count(pc, n_fix_waves);
+    fix_count(pc, n_fix_waves);
     return;
   }
   const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
