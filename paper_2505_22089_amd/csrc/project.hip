@@ -36,7 +36,13 @@ typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
 typedef __attribute__((address_space(1))) const u32x2 gcu32x2;
 typedef __attribute__((address_space(1))) const u32x4 gcu32x4;
 
-constexpr int kProjWaves = 8;
+#ifndef CHM_PROJ_WAVES
+#define CHM_PROJ_WAVES 8
+#endif
+#ifndef CHM_PROJ_GRID_PER_CU
+#define CHM_PROJ_GRID_PER_CU 2
+#endif
+constexpr int kProjWaves = CHM_PROJ_WAVES;
 constexpr int kProjWG = 64 * kProjWaves;
 
 __device__ __forceinline__ uint32_t bf16_bits_of_int(int v) {
@@ -64,7 +70,12 @@ __device__ __forceinline__ uint32_t bf16x2_of_bytes(uint32_t w, int i) {
 }
 
 template <bool FP32>
-__global__ __launch_bounds__(kProjWG, FP32 ? 2 : 3) void k_project(HashBatch hb, ProjConsts pc) {
+// waves per SIMD the bf16 variant is compiled for (VGPR budget 512 / this)
+#ifndef CHM_PROJ_WAVES_PER_SIMD
+#define CHM_PROJ_WAVES_PER_SIMD 4
+#endif
+__global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k_project(HashBatch hb,
+                                                                                     ProjConsts pc) {
   __shared__ uint16_t sW[kRowsPad * kWStride];
   __shared__ uint32_t sWords[kProjWaves][32 * 6];
   __shared__ float sRow[3][kRowsPad];     // tau_r, kappa_r, c_r (fp32)
@@ -400,7 +411,7 @@ hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, i
   hipError_t e = launch_fill_u32(pc.fixlist, 0u, 1, s);
   if (e != hipSuccess) return e;
   int grid = (tiles + kProjWaves - 1) / kProjWaves;
-  if (grid > 2 * n_cu) grid = 2 * n_cu;
+  if (grid > CHM_PROJ_GRID_PER_CU * n_cu) grid = CHM_PROJ_GRID_PER_CU * n_cu;
   if (grid * kProjWaves > kMaxProjWaves) grid = kMaxProjWaves / kProjWaves;
   ProjConsts p2 = pc;
   p2.n_waves = grid * kProjWaves;
