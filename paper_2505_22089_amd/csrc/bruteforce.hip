@@ -10,10 +10,11 @@
 // db columns it sees; lanes are merged with butterflies and splits by a
 // second kernel, which also applies the ratio test.
 //
-// The top-2 runs on packed keys 128 s + (127 - c), c the column inside its
-// 128-column LDS tile: one shift-add forms the key from the accumulator and
-// a per-column bias, a max and a median-of-three keep the two largest, and
-// the tile of the best key is recorded once per tile.  Ties between equal
+// The top-2 runs on packed keys T s + (T - 1 - c), c the column inside its
+// T-column LDS tile (|s| < 2^23, so T = 256 still fits int32): one
+// shift-add forms the key from the accumulator and a per-column bias, a max
+// and a median-of-three keep the two largest, and the tile of the best key
+// is recorded once per tile.  Ties between equal
 // scores cannot change the output (equal best and second distances fail
 // the ratio test for any t_r <= 1), so which column wins one is immaterial.
 #include <climits>
@@ -37,8 +38,16 @@ constexpr int kBfWaves = CHM_BF_WAVES;  // waves per work-group
 #endif
 constexpr int kBfRB = CHM_BF_ROWBLOCKS;
 constexpr int kBfQ = 32 * kBfRB * kBfWaves;  // queries per work-group
-static_assert(kBfWaves >= 4, "the 256 tile stagers are whole waves of the work-group");
-constexpr int kBfD = 128;            // db rows per LDS tile
+#ifndef CHM_BF_TILE
+#define CHM_BF_TILE 256
+#endif
+constexpr int kBfD = CHM_BF_TILE;    // db rows per LDS tile
+constexpr int kBfShift = kBfD == 256 ? 8 : 7;  // log2 kBfD
+static_assert(kBfD == 128 || kBfD == 256, "tile of 128 or 256 db rows");
+static_assert(64 * kBfWaves >= 2 * kBfD, "the tile stagers (two per row) are whole waves of the work-group");
+// Key of an empty column (a zero row past the db): below every real key
+// T s + (T - 1 - c) >= T (-2^22 - 2^21).
+constexpr int32_t kBfEmpty = INT_MIN / 2 - (1 << 29);
 constexpr int kBfStride = 144;       // bytes per staged row (pad spreads banks)
 constexpr int kBfTargetWG = 1024;    // aim for this many work-groups (splits of the db)
 
@@ -57,7 +66,7 @@ __device__ __forceinline__ void merge2(int32_t& s1, int32_t& j1, int32_t& s2, in
   j1 = nj;
 }
 
-__global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, int nq, const uint8_t* D,
+__global__ __launch_bounds__(64 * kBfWaves, 4) void k_bf_partial(const uint8_t* Q, int nq, const uint8_t* D,
                                                     int nd, int split_cols, int4* work) {
   __shared__ __attribute__((aligned(16))) uint8_t sD[kBfD * kBfStride];
   __shared__ int32_t sN[kBfD];
@@ -92,7 +101,7 @@ __global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, 
 
   for (int tile = c0; tile < c1; tile += kBfD) {
     __syncthreads();
-    // the first 256 threads stage the tile, half a row each: 64 bytes as
+    // the first 2 kBfD threads stage the tile, half a row each: 64 bytes as
     // four 16-byte pieces (whole waves, so the shuffle below is uniform)
     if (tid < 2 * kBfD) {
       const int row = tid >> 1, part = tid & 1;
@@ -108,9 +117,9 @@ __global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, 
         for (int w = 0; w < 4; ++w) nrm = __builtin_amdgcn_sdot4((int)v[w], (int)v[w], nrm, false);
       }
       nrm += __shfl_xor(nrm, 1);
-      // key bias of the column: -128 ||y'||^2 + (127 - c); an empty column
-      // (a zero row, dot 0) gets -2^30, below every real key
-      if (part == 0) sN[row] = (g < c1) ? -(nrm << 7) + (127 - row) : -(1 << 30);
+      // key bias of the column: -T ||y'||^2 + (T - 1 - c); an empty column
+      // (a zero row, dot 0) gets kBfEmpty, below every real key
+      if (part == 0) sN[row] = (g < c1) ? -(nrm << kBfShift) + (kBfD - 1 - row) : kBfEmpty;
     }
     __syncthreads();
     int32_t before[E];
@@ -134,7 +143,7 @@ __global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, 
       for (int rb = 0; rb < kBfRB; ++rb) {
 #pragma unroll
         for (int e = 0; e < 16; ++e) {
-          const int32_t key = (acc[rb][e] << 8) + bias;  // 128 (2 x'.y' - ||y'||^2) + 127 - c
+          const int32_t key = (acc[rb][e] << (kBfShift + 1)) + bias;  // T (2 x'.y' - ||y'||^2) + T - 1 - c
           s2[16 * rb + e] = med3i(s1[16 * rb + e], s2[16 * rb + e], key);
           s1[16 * rb + e] = max(s1[16 * rb + e], key);
         }
@@ -147,7 +156,7 @@ __global__ __launch_bounds__(64 * kBfWaves) void k_bf_partial(const uint8_t* Q, 
   // from here on a best key travels with its global column
   int32_t j1[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) j1[e] = s1[e] == INT_MIN ? -1 : t1[e] + (127 - (s1[e] & 127));
+  for (int e = 0; e < E; ++e) j1[e] = s1[e] == INT_MIN ? -1 : t1[e] + (kBfD - 1 - (s1[e] & (kBfD - 1)));
 #pragma unroll
   for (int e = 0; e < E; ++e) {
 #pragma unroll
@@ -181,8 +190,8 @@ __global__ void k_bf_merge(const int4* work, int splits, const uint8_t* Q, int n
     out[i] = -1;
     return;
   }
-  // keys back to scores: s = key >> 7 (arithmetic)
-  const int64_t e1 = (int64_t)nrm - (s1 >> 7), e2 = (int64_t)nrm - (s2 >> 7);
+  // keys back to scores: s = key >> log2 T (arithmetic)
+  const int64_t e1 = (int64_t)nrm - (s1 >> kBfShift), e2 = (int64_t)nrm - (s2 >> kBfShift);
   out[i] = ((int64_t)rb * rb * e1 < (int64_t)ra * ra * e2) ? j1 : -1;
 }
 

@@ -23,7 +23,8 @@ def gpu_bruteforce(Xq, Xd, ratio=(4, 5)):
 
 
 @pytest.mark.parametrize("nq,nd", [(0, 5), (1, 0), (1, 1), (1, 2), (100, 127), (129, 128),
-                                   (129, 129), (300, 1000), (33, 4097)])
+                                   (129, 129), (50, 255), (257, 256), (70, 257), (513, 511),
+                                   (300, 1000), (33, 4097)])
 def test_bruteforce_shapes(nq, nd):
     rng = np.random.default_rng(nq * 7 + nd)
     A = synth.sift_like(rng, nq)
