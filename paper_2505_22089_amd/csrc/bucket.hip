@@ -18,9 +18,10 @@
 // each wavefront owns a contiguous segment of descriptors.  Pass 1 counts
 // per (wavefront, bucket) and finds each bucket's first member; a scan turns
 // the counts into each wavefront's starting position inside each bucket;
-// pass 2 scatters, ranking equal ids inside a 64-lane chunk with ballots
-// (lanes agreeing on every id bit), so the order inside a bucket is the
-// descriptor order; the pads are written last.
+// pass 2 scatters, ranking equal ids inside a 64-lane chunk by the lanes'
+// bits in a per-wavefront LDS mask of each bucket (each lane ORs its bit in:
+// the rank is the count of lower lanes with the same id), so the order
+// inside a bucket is the descriptor order; the pads are written last.
 #include "chm_internal.h"
 
 namespace chm {
@@ -29,19 +30,25 @@ constexpr int kBucketWG = 1024;
 constexpr int kBucketWaves = kBucketWG / 64;
 constexpr int kBucketMaxN = 65536;
 
-__device__ __forceinline__ uint64_t peers_of(uint32_t b, bool valid, int m) {
-  uint64_t peers = __ballot(valid);
-  for (int bit = 0; bit < m; ++bit) {
-    const bool set = (b >> bit) & 1u;
-    const uint64_t bm = __ballot(valid && set);
-    peers &= set ? bm : ~bm;
-  }
+// Lanes of this wavefront's 64-element chunk holding the same bucket id as
+// this lane: every valid lane ORs its bit into the wavefront's mask of its
+// bucket, reads the mask back, and the mask is cleared again after all
+// lanes have read it (a wavefront's LDS operations run in program order).
+__device__ __forceinline__ uint64_t peers_of(unsigned long long* mask, uint32_t b, bool valid) {
+  const int lane = __lane_id();
+  if (valid) atomicOr(&mask[b], 1ull << lane);
+  __builtin_amdgcn_wave_barrier();
+  const uint64_t peers = valid ? mask[b] : 0ull;
+  __builtin_amdgcn_wave_barrier();
+  if (valid && (peers & ((1ull << lane) - 1ull)) == 0) mask[b] = 0ull;
+  __builtin_amdgcn_wave_barrier();
   return peers;
 }
 
 __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   extern __shared__ uint8_t sId[];  // the table's ids (dynamic: the batch's largest n_pad)
   __shared__ uint32_t cnt[kBucketWaves][256];
+  __shared__ unsigned long long peer[kBucketWaves][256];  // per wavefront, zero between chunks
   __shared__ uint32_t first[256];   // smallest member of each bucket
   __shared__ uint32_t real[256];    // members of each bucket
   __shared__ uint32_t pbase[256];   // padded start of each bucket
@@ -60,7 +67,10 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   // stage ids (n_pad is a multiple of 8 and the table start is 8-byte aligned)
   for (int i = tid; i < I.n_pad / 8; i += kBucketWG)
     reinterpret_cast<uint2*>(sId)[i] = reinterpret_cast<const uint2*>(ids)[i];
-  for (int i = tid; i < kBucketWaves * 256; i += kBucketWG) (&cnt[0][0])[i] = 0;
+  for (int i = tid; i < kBucketWaves * 256; i += kBucketWG) {
+    (&cnt[0][0])[i] = 0;
+    (&peer[0][0])[i] = 0ull;
+  }
   for (int i = tid; i < 256; i += kBucketWG) first[i] = 0xFFFFFFFFu;
   __syncthreads();
 
@@ -74,7 +84,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const int i = c * 64 + lane;
     const bool valid = i < n;
     const uint32_t b = valid ? sId[i] : 0u;
-    const uint64_t peers = peers_of(b, valid, hb.m);
+    const uint64_t peers = peers_of(peer[wave], b, valid);
     if (valid && (peers & lt) == 0) {
       cnt[wave][b] += (uint32_t)__popcll(peers);
       atomicMin(&first[b], (uint32_t)i);
@@ -131,7 +141,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const int i = c * 64 + lane;
     const bool valid = i < n;
     const uint32_t b = valid ? sId[i] : 0u;
-    const uint64_t peers = peers_of(b, valid, hb.m);
+    const uint64_t peers = peers_of(peer[wave], b, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t start = valid ? cnt[wave][b] : 0u;
     if (valid) {
