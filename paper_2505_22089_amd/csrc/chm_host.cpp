@@ -530,6 +530,15 @@ static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
   return d;
 }
 
+#ifndef CHM_TAIL_PERCENT
+#define CHM_TAIL_PERCENT 8
+#endif
+static constexpr int kTailPercent = CHM_TAIL_PERCENT;
+#ifndef CHM_TAIL_PIECES
+#define CHM_TAIL_PIECES 2
+#endif
+static constexpr int kTailPieces = CHM_TAIL_PIECES;
+
 chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
                            int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream,
                            chm_plan** out, bool wait_upload) {
@@ -625,6 +634,25 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
       const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
       load[b] += g.first;
       for (auto& x : *g.second) bins[b].push_back(x.second);
+    }
+    // The items that make up the last kTailPercent of a bin's cost are cut
+    // into kTailPieces pieces (whole wavefront chunks), so that the
+    // work-groups draining the bins finish within a smaller item of each
+    // other rather than a full one.
+    for (int b = 0; b < nbins && kTailPercent > 0; ++b) {
+      std::vector<WorkItem>& v = bins[b];
+      auto cost = [&](const WorkItem& w) { return (double)(w.q1 - w.q0) * (double)(pd[w.pair].d.n + 64); };
+      double total = 0, tail = 0;
+      for (const WorkItem& w : v) total += cost(w);
+      size_t cut = v.size();
+      while (cut > 0 && tail < total * kTailPercent / 100.0) tail += cost(v[--cut]);
+      std::vector<WorkItem> out(v.begin(), v.begin() + cut);
+      for (size_t i = cut; i < v.size(); ++i) {
+        const WorkItem& w = v[i];
+        const int piece = std::max(64, ((w.q1 - w.q0 + kTailPieces - 1) / kTailPieces + 63) / 64 * 64);
+        for (int q0 = w.q0; q0 < w.q1; q0 += piece) out.push_back({w.pair, q0, std::min(w.q1, q0 + piece), w.lds});
+      }
+      v.swap(out);
     }
     pl->bins[0] = 0;
     for (int b = 0; b < nbins; ++b) {
