@@ -14,8 +14,8 @@ grid-5000x10000 instead runs the whole MBR-scheduled job (Algorithm 1) from
 pinned host memory under GPU residency caps (default 16 GB and 2 GB):
 descriptors loaded and freed per block row, hashed and matched on the GPU.
 
-Prints one JSON line.  --gpus N > 1 is not supported: this build runs on one
-GPU.
+Prints one JSON line.  --gpus N > 1 is not supported: the path runs on one
+GPU (pairs would be sharded by contiguous ranges of block rows, one per GPU).
 """
 import argparse
 import json
@@ -66,8 +66,8 @@ def parse():
 def main():
     args = parse()
     if args.gpus != 1:
-        print("bench.py runs on one GPU only (--gpus %d requested); multi-GPU sharding is "
-              "described in DESIGN.md but not built" % args.gpus, file=sys.stderr)
+        print("bench.py runs on one GPU only (--gpus %d requested); sharding over several "
+              "GPUs is not built" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.copy_calibration:
         return copy_calibration()

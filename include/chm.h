@@ -43,7 +43,7 @@ extern "C" {
 typedef enum chm_status {
   CHM_OK = 0,
   CHM_E_INVALID_ARG = -1,  /* a size, pointer or parameter is out of range */
-  CHM_E_UNSUPPORTED = -2,  /* a valid request this build does not support */
+  CHM_E_UNSUPPORTED = -2,  /* a valid request the library does not support */
   CHM_E_CAPACITY = -3,     /* the arena (or a cap) cannot hold what was asked */
   CHM_E_NOT_RESIDENT = -4, /* a pair names an image that is not loaded */
   CHM_E_HIP = -5,          /* a HIP runtime call failed */
