@@ -32,7 +32,7 @@ METRIC = "matched image pairs/sec at 8k feats/image (batched vs plain), bit-exac
 HBM_PEAK_GBS = 8000.0
 # 32-bit integer VALU lane-ops per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-DEFAULT_TUNING = dict(queries_per_item=2048, wg_threads=1024, lds_codes=1, grid_per_cu=1)
+DEFAULT_TUNING = dict(queries_per_item=3072, wg_threads=1024, lds_codes=1, grid_per_cu=1)
 
 
 def parse():

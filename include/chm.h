@@ -233,7 +233,12 @@ chm_status chm_match_pairs(chm_store *store, const int32_t *h_pairs, int32_t n_p
 /* Launch-shape tuning of the match kernels (chosen by the autotuner; any
  * valid value gives identical results). */
 typedef struct chm_tuning {
-  int32_t queries_per_item; /* queries per batched work item, multiple of 64, 64..8192 */
+  int32_t queries_per_item; /* queries per batched work item, multiple of 64,
+                               64..8192 (default 3072).  Batched plans shrink
+                               items where a larger one would not sort in LDS,
+                               cap them at 512 in launches that stage no db
+                               image, and halve those ending each XCD bin's
+                               work. */
   int32_t wg_threads;       /* 256 or 1024 */
   int32_t lds_codes;        /* 1: stage the db image's codes in LDS when they fit */
   int32_t grid_per_cu;      /* persistent work-groups per compute unit when no db

@@ -22,6 +22,7 @@ from . import chm
 CANDIDATES: List[Dict[str, int]] = [
     dict(queries_per_item=1024, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=2048, wg_threads=1024, lds_codes=1, grid_per_cu=1),
+    dict(queries_per_item=3072, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=4096, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=512, wg_threads=1024, lds_codes=1, grid_per_cu=1),
     dict(queries_per_item=1024, wg_threads=256, lds_codes=1, grid_per_cu=1),

@@ -94,7 +94,10 @@ hipError_t sao_run(int32_t first, int32_t count, int32_t table_pairs, int32_t n_
 // kSortMax queries is processed in order of walk length when its order fits
 // above the stage, else in query order.  The HBM-only kernel's LDS is the
 // order array and the top.
-constexpr int kSortMax = 2048;
+#ifndef CHM_SORT_MAX
+#define CHM_SORT_MAX 4096
+#endif
+constexpr int kSortMax = CHM_SORT_MAX;
 constexpr size_t kLdsTop = 16 + 256 * 4;
 constexpr size_t kMatchLdsTail = 2 * kSortMax + kLdsTop;
 constexpr size_t kLdsTotal = 160 * 1024;

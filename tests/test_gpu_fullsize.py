@@ -142,10 +142,10 @@ def test_db_images_around_the_lds_stage_limits():
     # Limits of the layout on a CU with 160 KiB of LDS (L = 6, m = 8): the
     # control words and histogram take the top 1040 bytes; codes take 16 B a
     # point from address 0; offsets (6 x 257 int32, 6176 B) join them when a
-    # 2048-query sort order (4096 B) still fits; an item's order takes 2 B a
+    # 4096-query sort order (8192 B) still fits; an item's order takes 2 B a
     # query.  On another LDS size the same images are still valid inputs.
     top = 160 * 1024 - 1040
-    offsets_staged = (top - 6176 - 4096) // 16        # 9533
+    offsets_staged = (top - 6176 - 8192) // 16        # 9277
     sorted_1024 = (top - 2 * 1024) // 16              # 10047
     codes = top // 16                                 # 10175
     sizes = [offsets_staged, offsets_staged + 1, 10000, sorted_1024, sorted_1024 + 1, codes, codes + 1,
@@ -157,7 +157,7 @@ def test_db_images_around_the_lds_stage_limits():
     st = new_store(wl)
     load_all(st, wl.images)
     ref = oracle_slices(wl, wl.pairs)
-    for tuning in ((2048, 1024, 1, 1), (512, 1024, 1, 1), (1536, 1024, 1, 1)):
+    for tuning in ((3072, 1024, 1, 1), (2048, 1024, 1, 1), (512, 1024, 1, 1), (1536, 1024, 1, 1)):
         st.set_tuning(*tuning)
         out, _, offs = run_match(st, wl.pairs)
         for p in range(len(wl.pairs)):
