@@ -184,6 +184,21 @@ def test_match_parity_arena_low_dword_above_2gib(mode):
     st.close()
 
 
+@pytest.mark.parametrize("ratio", [(99, 100), (1, 1), (1, 2)])
+@pytest.mark.parametrize("mode", [chm.MATCH_PLAIN, chm.MATCH_BATCHED])
+def test_match_parity_ratio(mode, ratio):
+    """Ratio thresholds near and at 1 stress the exact test
+    den^2 * d1 < num^2 * d2 in 64-bit integers (at 1/1 a query passes only
+    when its nearest candidate is strictly closer than the second)."""
+    wl = small_workload([1200, 900, 300], seed=7 + ratio[0], copies=0.3)
+    wl.ratio = ratio
+    st = new_store(wl)
+    load_all(st, wl.images)
+    out = check_matches(st, wl, [(0, 1), (1, 0), (2, 0), (1, 1)], mode, wl.K)
+    assert (out >= 0).any()
+    st.close()
+
+
 @pytest.mark.parametrize("K", [1, 2, 3, 8, 16, 32])
 def test_match_parity_k(K):
     wl = small_workload([900, 700, 0, 1], seed=K)
