@@ -32,7 +32,6 @@ METRIC = "matched image pairs/sec at 8k feats/image (batched vs plain), bit-exac
 HBM_PEAK_GBS = 8000.0
 # 32-bit integer VALU lane-ops per second: 256 CUs x 4 SIMD x 16 lanes x 2.4 GHz
 ALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
-DEFAULT_TUNING = dict(queries_per_item=3072, wg_threads=1024, lds_codes=1, grid_per_cu=1)
 
 
 def parse():
@@ -58,8 +57,8 @@ def parse():
                     help="also time the plain path re-hashing both images of every pair "
                          "(always on for the benchmark workload)")
     ap.add_argument("--tuning", default="default",
-                    help="'default' (the library's), 'auto' (autotuner), or "
-                         "queries_per_item,wg_threads,lds_codes,grid_per_cu")
+                    help="'default' (the library's), 'auto' (autotuner), or comma-separated "
+                         "name=value chm_tuning fields")
     return ap.parse_args()
 
 
@@ -90,8 +89,11 @@ def main():
     prec = chm.PROJ_FP32 if args.precision == "fp32" else chm.PROJ_BF16
     cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio, precision=prec)
     need = chm.store_overhead_bytes(cfg) + sum(chm.image_bytes(cfg, x.shape[0]) + 256 for x in wl.images)
-    arena = torch.empty(need + (64 << 20), dtype=torch.uint8, device=dev)
+    # room beyond the images for the plans: work lists and the bucket-major
+    # kept lists (32 B per query of every pair at K = 8)
+    arena = torch.empty(need + (640 << 20), dtype=torch.uint8, device=dev)
     store = chm.Store(cfg, wl.W, wl.mu, arena)
+    lib_tuning = store.tuning_dict()
     descs = [torch.from_numpy(x).to(dev) for x in wl.images]
     ids = list(range(n_img))
     store.load(ids, descs)
@@ -161,12 +163,11 @@ def main():
         from paper_2505_22089_amd import autotune
         best = autotune.tune(store, wl.pairs, reps=3, cache=None)
     else:
-        store.set_tuning(**DEFAULT_TUNING)
+        store.set_tuning(**lib_tuning)
         if args.tuning != "default":
-            v = [int(t) for t in args.tuning.split(",")]
-            store.set_tuning(**dict(zip(("queries_per_item", "wg_threads", "lds_codes", "grid_per_cu"), v)))
-        t = store.tuning()
-        best = {k: int(getattr(t, k)) for k in DEFAULT_TUNING}
+            # name=value pairs of chm_tuning fields, e.g. match_kernel=0,queries_per_item=2048
+            store.set_tuning(**{k: int(v) for k, v in (kv.split("=") for kv in args.tuning.split(","))})
+        best = store.tuning_dict()
     with torch.cuda.stream(stream):
         plan_b = chm.Plan(store, wl.pairs, offs, out_b, None, chm.MATCH_BATCHED, stream)
 

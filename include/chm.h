@@ -35,7 +35,7 @@
 extern "C" {
 #endif
 
-#define CHM_ABI_VERSION 1
+#define CHM_ABI_VERSION 2
 #define CHM_DIM 128       /* descriptor dimension (SIFT) */
 #define CHM_CODE_BITS 128 /* n, bits of the long code (Sec. 2.3.1 step (2), n = 128) */
 #define CHM_MAX_FEATS 65535
@@ -244,7 +244,30 @@ typedef struct chm_tuning {
   int32_t grid_per_cu;      /* persistent work-groups per compute unit when no db
                                image of a batched plan is staged in LDS, 1..8 (a
                                launch that stages runs one per compute unit) */
+  int32_t match_kernel;     /* batched plans: CHM_KERNEL_QUERY_MAJOR (one lane per
+                               query walking its own buckets, the fields above)
+                               for every pair, or CHM_KERNEL_BUCKET_MAJOR
+                               (default): pairs whose db image has at least
+                               bm_min_db_feats points run bucket major (one
+                               launch per table, the lanes of a wavefront
+                               sharing one db bucket), the others query major
+                               (with CHM_WHOLE_LAST_BUCKET, and when the kept
+                               lists do not fit the arena, all run query major) */
+  int32_t bm_min_db_feats;  /* see match_kernel, 0..65536 (default 10176, the
+                               first size above the query-major LDS code stage) */
+  int32_t group_queries;    /* bucket major: pairs with the same db image are
+                               grouped while their query images hold at most this
+                               many descriptors together (at most 32 pairs),
+                               1..1048576 (default 98304) */
+  int32_t tail_percent;     /* query major, batched: the items making up the last
+                               tail_percent of each XCD bin's work are halved,
+                               0..50 (default 8) */
+  int32_t hbm_item_queries; /* query major, batched launches that stage no db
+                               image in LDS: queries per item, multiple of 64,
+                               64..8192 (default 512) */
 } chm_tuning;
+
+enum { CHM_KERNEL_QUERY_MAJOR = 0, CHM_KERNEL_BUCKET_MAJOR = 1 };
 
 chm_status chm_store_get_tuning(const chm_store *store, chm_tuning *out);
 chm_status chm_store_set_tuning(chm_store *store, const chm_tuning *tuning);

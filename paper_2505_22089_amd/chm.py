@@ -18,7 +18,7 @@ import numpy as np
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libchm.so")
 
-ABI_VERSION = 1
+ABI_VERSION = 2
 ACCEPT_SINGLE = 1
 WHOLE_LAST_BUCKET = 2
 PROJ_BF16, PROJ_FP32 = 0, 1
@@ -50,7 +50,14 @@ class Stats(C.Structure):
 
 class Tuning(C.Structure):
     _fields_ = [("queries_per_item", C.c_int32), ("wg_threads", C.c_int32),
-                ("lds_codes", C.c_int32), ("grid_per_cu", C.c_int32)]
+                ("lds_codes", C.c_int32), ("grid_per_cu", C.c_int32),
+                ("match_kernel", C.c_int32), ("bm_min_db_feats", C.c_int32), ("group_queries", C.c_int32),
+                ("tail_percent", C.c_int32), ("hbm_item_queries", C.c_int32)]
+
+
+TUNING_FIELDS = [f for f, _ in Tuning._fields_]
+KERNEL_QUERY_MAJOR = 0
+KERNEL_BUCKET_MAJOR = 1
 
 
 # every symbol include/chm.h declares
@@ -251,13 +258,22 @@ class Store:
         _check(lib().chm_store_get_tuning(self.handle, C.byref(t)))
         return t
 
-    def set_tuning(self, queries_per_item=None, wg_threads=None, lds_codes=None, grid_per_cu=None):
+    def set_tuning(self, queries_per_item=None, wg_threads=None, lds_codes=None, grid_per_cu=None, **more):
+        """Changes the named fields of the store's chm_tuning (the others keep
+        their values); keyword names are the fields of Tuning."""
         t = self.tuning()
-        for k, v in (("queries_per_item", queries_per_item), ("wg_threads", wg_threads),
-                     ("lds_codes", lds_codes), ("grid_per_cu", grid_per_cu)):
+        vals = dict(queries_per_item=queries_per_item, wg_threads=wg_threads, lds_codes=lds_codes,
+                    grid_per_cu=grid_per_cu, **more)
+        for k, v in vals.items():
+            if k not in TUNING_FIELDS:
+                raise TypeError("unknown tuning field %s" % k)
             if v is not None:
                 setattr(t, k, int(v))
         _check(lib().chm_store_set_tuning(self.handle, C.byref(t)))
+
+    def tuning_dict(self) -> dict:
+        t = self.tuning()
+        return {k: int(getattr(t, k)) for k in TUNING_FIELDS}
 
     def debug_image(self, image_id: int, stream=None):
         """Internal arrays of a resident image as device tensors."""

@@ -102,7 +102,10 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
       uint32_t s = 0;
       if (b < nb)
         for (int w = 0; w < kBucketWaves; ++w) s += cnt[w][b];
-      if (b < nb) real[b] = s;
+      if (b < nb) {
+        real[b] = s;
+        I.counts[t * nb + b] = (int32_t)s;
+      }
       tot[k] = (s + 7u) & ~7u;
       run += tot[k];
     }

@@ -225,6 +225,11 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   S->tuning.wg_threads = 1024;
   S->tuning.lds_codes = 1;
   S->tuning.grid_per_cu = 1;
+  S->tuning.match_kernel = CHM_KERNEL_BUCKET_MAJOR;
+  S->tuning.bm_min_db_feats = lds_code_cap() + 1;
+  S->tuning.group_queries = 98304;
+  S->tuning.tail_percent = 8;
+  S->tuning.hbm_item_queries = 512;
   hipError_t e = hipMemcpy(S->dW, W.data(), W.size() * 2, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dTau, tau.data(), tau.size() * 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipMemcpy(S->dCmu, cmu.data(), cmu.size() * 8, hipMemcpyHostToDevice);
@@ -504,6 +509,15 @@ extern "C" chm_status chm_store_set_tuning(chm_store* S, const chm_tuning* t) {
     return fail(CHM_E_INVALID_ARG, "wg_threads must be 256 or 1024");
   if (t->lds_codes != 0 && t->lds_codes != 1) return fail(CHM_E_INVALID_ARG, "lds_codes must be 0 or 1");
   if (t->grid_per_cu < 1 || t->grid_per_cu > 8) return fail(CHM_E_INVALID_ARG, "grid_per_cu must be 1..8");
+  if (t->match_kernel != CHM_KERNEL_QUERY_MAJOR && t->match_kernel != CHM_KERNEL_BUCKET_MAJOR)
+    return fail(CHM_E_INVALID_ARG, "match_kernel must be CHM_KERNEL_QUERY_MAJOR or CHM_KERNEL_BUCKET_MAJOR");
+  if (t->bm_min_db_feats < 0 || t->bm_min_db_feats > 65536)
+    return fail(CHM_E_INVALID_ARG, "bm_min_db_feats must be 0..65536");
+  if (t->group_queries < 1 || t->group_queries > (1 << 20))
+    return fail(CHM_E_INVALID_ARG, "group_queries must be 1..1048576");
+  if (t->tail_percent < 0 || t->tail_percent > 50) return fail(CHM_E_INVALID_ARG, "tail_percent must be 0..50");
+  if (t->hbm_item_queries < 64 || t->hbm_item_queries > 8192 || t->hbm_item_queries % 64)
+    return fail(CHM_E_INVALID_ARG, "hbm_item_queries must be a multiple of 64 in 64..8192");
   S->tuning = *t;
   return CHM_OK;
 }
@@ -522,26 +536,151 @@ static ImageDev image_dev(const chm_store* S, const ImageSlot& sl) {
   d.ids = h.ids;
   d.norms = h.norms;
   d.offsets = h.offsets;
+  d.counts = h.counts;
   d.members = h.members;
   d.tcodes = h.tcodes;
   d.n = h.n;
   d.n_pad = h.n_pad;
   d.m_stride = h.m_stride;
+  d.reserved = 0;
   return d;
 }
 
-#ifndef CHM_TAIL_PERCENT
-#define CHM_TAIL_PERCENT 8
-#endif
-static constexpr int kTailPercent = CHM_TAIL_PERCENT;
-#ifndef CHM_TAIL_PIECES
-#define CHM_TAIL_PIECES 2
-#endif
-static constexpr int kTailPieces = CHM_TAIL_PIECES;
-#ifndef CHM_HBM_ITEM_QUERIES
-#define CHM_HBM_ITEM_QUERIES 512
-#endif
-static constexpr int kHbmItemQueries = CHM_HBM_ITEM_QUERIES;
+// Query-major batched plans halve the items that end each bin (the tail
+// fraction is chm_tuning.tail_percent).
+static constexpr int kTailPieces = 2;
+
+// Kept-list state of the bucket-major part of a plan: at most this much
+// arena per round.
+static constexpr uint64_t kBmStateMax = 512ull << 20;
+static constexpr int kBmMaxGroupPairs = 32;
+
+static int kept_slots(int K) { return K <= 2 ? 2 : K <= 4 ? 4 : K <= 8 ? 8 : K <= 16 ? 16 : 32; }
+
+// The bucket-major part of a batched plan, before upload.
+struct BmPart {
+  std::vector<int> order;        // the part's pairs (indices into pd) in group order
+  std::vector<int64_t> st_off;   // state row of each, per order position
+  std::vector<int32_t> ints;     // group ranges (absolute pair indices), then the rounds' bin tables
+  std::vector<chm_plan::BmRound> rounds;
+  int groups = 0;
+};
+
+// Groups the pairs idx (into pd) for bucket-major matching: ordered by db
+// image, a group holds pairs with one db image whose query images have at
+// most tuning.group_queries descriptors together (at most kBmMaxGroupPairs
+// pairs).  Groups go into rounds whose kept lists (KT keys per query) fit
+// one state block of the arena (allocated here), and inside a round into
+// one bin per XCD, most expensive first onto the least loaded bin.  The
+// part's pairs will sit at first_pair.. of the plan's pair array.
+// CHM_E_CAPACITY when not even one group's lists fit.
+static chm_status bm_part(chm_store* S, chm_plan* pl, const std::vector<PairDev>& pd, const std::vector<int>& idx,
+                          int first_pair, uint64_t keep_free, BmPart* bp) {
+  const int P = (int)idx.size();
+  const int L = S->cfg.num_tables;
+  const uint64_t row_bytes = 4ull * (uint64_t)kept_slots(S->cfg.top_k);
+  const int nbins = std::max(1, S->n_xcd);
+  std::vector<int>& ord = bp->order;
+  ord = idx;
+  std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+    if (pd[x].d.codes != pd[y].d.codes) return pd[x].d.codes < pd[y].d.codes;
+    return pd[x].q.codes < pd[y].q.codes;
+  });
+  std::vector<int> gstart;
+  int64_t gq = 0;
+  for (int i = 0; i < P; ++i) {
+    const PairDev& x = pd[ord[i]];
+    const bool fresh = i == 0 || x.d.codes != pd[ord[i - 1]].d.codes || i - gstart.back() >= kBmMaxGroupPairs ||
+                       (gq + x.q.n > pl->tun.group_queries && gq > 0);
+    if (fresh) {
+      gstart.push_back(i);
+      gq = 0;
+    }
+    gq += x.q.n;
+  }
+  const int G = (int)gstart.size();
+  gstart.push_back(P);
+  std::vector<uint64_t> gstate(G, 0);
+  std::vector<double> gcost(G, 0.0);
+  uint64_t total_state = 0, max_state = 0;
+  for (int g = 0; g < G; ++g) {
+    for (int i = gstart[g]; i < gstart[g + 1]; ++i) {
+      const PairDev& x = pd[ord[i]];
+      gstate[g] += row_bytes * (uint64_t)x.q.n;
+      gcost[g] += (double)x.q.n * (double)(x.d.n + 64);
+    }
+    gstate[g] = round_up(gstate[g], 256);
+    total_state += gstate[g];
+    max_state = std::max(max_state, gstate[g]);
+  }
+  // the state block: all groups' lists if they fit, else the largest block
+  // (halving) that still holds the largest group; L = 1 keeps no lists.
+  // keep_free bytes stay free for the rest of the plan (reserved meanwhile).
+  uint64_t want = L > 1 ? std::min(total_state, std::max(kBmStateMax, max_state)) : 0;
+  if (want > 0) {
+    uint64_t keep_off = 0;
+    const bool kept = S->arena.alloc(keep_free, &keep_off);
+    if (!kept) return fail(CHM_E_CAPACITY, "arena cannot hold the plan");
+    bool got = false;
+    for (;;) {
+      if (S->arena.alloc(want, &pl->state_off)) {
+        got = true;
+        break;
+      }
+      if (want / 2 < max_state) break;
+      want = std::max(max_state, round_up(want / 2, 256));
+    }
+    S->arena.release(keep_off, keep_free);
+    if (!got) return fail(CHM_E_CAPACITY, "arena cannot hold the kept lists of a group");
+    pl->state_bytes = want;
+    pl->dState = (uint32_t*)(S->base + pl->state_off);
+  }
+  std::vector<std::vector<int>> rounds;
+  uint64_t used = 0;
+  for (int g = 0; g < G; ++g) {
+    if (rounds.empty() || (want > 0 && used + gstate[g] > want)) {
+      rounds.emplace_back();
+      used = 0;
+    }
+    rounds.back().push_back(g);
+    used += gstate[g];
+  }
+  bp->st_off.assign(P, 0);
+  bp->ints.clear();
+  for (int g = 0; g <= G; ++g) bp->ints.push_back(first_pair + gstart[g]);
+  for (auto& r : rounds) {
+    uint64_t row = 0;
+    for (int g : r)
+      for (int i = gstart[g]; i < gstart[g + 1]; ++i) {
+        bp->st_off[i] = (int64_t)row;
+        row += (uint64_t)pd[ord[i]].q.n;
+      }
+    std::vector<int> og(r);
+    std::stable_sort(og.begin(), og.end(), [&](int x, int y) { return gcost[x] > gcost[y]; });
+    std::vector<std::vector<int>> bins(nbins);
+    std::vector<double> load(nbins, 0.0);
+    for (int g : og) {
+      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+      load[b] += gcost[g];
+      bins[b].push_back(g);
+    }
+    chm_plan::BmRound br;
+    br.begin_off = (int)bp->ints.size();
+    br.max_groups = 0;
+    int acc = 0;
+    for (int b = 0; b < nbins; ++b) {
+      bp->ints.push_back(acc);
+      acc += (int)bins[b].size();
+      br.max_groups = std::max(br.max_groups, (int)bins[b].size());
+    }
+    bp->ints.push_back(acc);
+    br.list_off = (int)bp->ints.size();
+    for (int b = 0; b < nbins; ++b) bp->ints.insert(bp->ints.end(), bins[b].begin(), bins[b].end());
+    bp->rounds.push_back(br);
+  }
+  bp->groups = G;
+  return CHM_OK;
+}
 
 chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, const int64_t* starts,
                            int32_t* d_out, uint32_t* d_topk, int32_t mode, void* stream,
@@ -559,6 +698,7 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
     pd[p].q = image_dev(S, iq->second);
     pd[p].d = image_dev(S, id->second);
     pd[p].out_off = starts[p];
+    pd[p].st_off = 0;
     total_out += iq->second.n;
     gens[iq->first] = iq->second.gen;
     gens[id->first] = id->second.gen;
@@ -576,111 +716,157 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   const int ldsmax = pl->tun.lds_codes ? lds_max_feats(S) : 0;
   pl->lds_max = ldsmax;
 
+  // Batched plans match pairs whose db image has at least
+  // tuning.bm_min_db_feats points bucket major, the others query major.
+  std::vector<int> qm_idx, bm_idx;
+  const bool bm_ok = mode == CHM_MATCH_BATCHED && pl->tun.match_kernel == CHM_KERNEL_BUCKET_MAJOR &&
+                     !(S->cfg.flags & CHM_WHOLE_LAST_BUCKET);
+  for (int p = 0; p < P; ++p) (bm_ok && pd[p].d.n >= pl->tun.bm_min_db_feats ? bm_idx : qm_idx).push_back(p);
+  BmPart bp;
+  if (!bm_idx.empty()) {
+    // room the rest of the plan may need: all pairs, one query-major item
+    // per 64 queries and pair, the queue and bin words, the group tables
+    uint64_t items_max = 0;
+    for (const PairDev& x : pd) items_max += (uint64_t)(x.q.n + 63) / 64 + 1;
+    const uint64_t keep_free = round_up(sizeof(PairDev) * (uint64_t)P, 256) + round_up(sizeof(WorkItem) * items_max, 256) +
+                               512 + round_up(4ull * (uint64_t)bm_idx.size() * (uint64_t)(std::max(1, S->n_xcd) + 3) + 4, 256);
+    const chm_status bst = bm_part(S, pl, pd, bm_idx, (int)qm_idx.size(), keep_free, &bp);
+    if (bst == CHM_E_CAPACITY) {  // the kept lists do not fit the arena: all query major
+      clear_error();
+      qm_idx.insert(qm_idx.end(), bm_idx.begin(), bm_idx.end());
+      std::sort(qm_idx.begin(), qm_idx.end());
+      bm_idx.clear();
+      bp = BmPart();
+    } else if (bst) {
+      delete pl;
+      return bst;
+    }
+  }
+  // the plan's pair array: the query-major pairs in input order, then the
+  // bucket-major ones in group order
+  std::vector<PairDev> fp;
+  fp.reserve(P);
+  for (int p : qm_idx) fp.push_back(pd[p]);
+  for (size_t i = 0; i < bp.order.size(); ++i) {
+    fp.push_back(pd[bp.order[i]]);
+    fp.back().st_off = bp.st_off[i];
+  }
+
   std::vector<WorkItem> items;
-  if (mode == CHM_MATCH_PLAIN) {
-    const int qp = pl->tun.wg_threads;
-    pl->pair_begin.resize(P);
-    pl->pair_count.resize(P);
-    pl->pair_lds.resize(P);
-    for (int p = 0; p < P; ++p) {
-      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
-      pl->pair_begin[p] = (int)items.size();
-      for (int q0 = 0; q0 < pd[p].q.n; q0 += qp)
-        items.push_back({p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0});
-      pl->pair_count[p] = (int)items.size() - pl->pair_begin[p];
-      pl->pair_lds[p] = lds;
-    }
-  } else {
-    // All items go to one persistent launch: the LDS-staging kernel when any
-    // db image fits the code stage (it reads larger ones from HBM in the same
-    // launch), else the HBM-only kernel.  Items are dealt into one bin per
-    // XCD, whole db images at a time (largest total first onto the least
-    // loaded bin), so the work-groups of an XCD share the db images' codes,
-    // members and descriptors in their L2; inside a bin, a db image's items
-    // are consecutive, longest first.
-    const int qpi = pl->tun.queries_per_item;
-    const int nbins = std::max(1, S->n_xcd);
-    std::map<const void*, std::vector<std::pair<double, WorkItem>>> groups;
-    for (int p = 0; p < P; ++p) pl->lds_launch |= ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
-    for (int p = 0; p < P; ++p) {
-      const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
-      // Above a large stage an item's sort order may not fit: such pairs
-      // take items small enough to sort, down to one query per thread of a
-      // 1024-thread work-group; below that they keep full items, unsorted.
-      // A launch without any staged pair takes items of at most
-      // kHbmItemQueries queries.
-      int qp = qpi;
-      if (lds) {
-        const int room = lds_sort_room(S->lds_top, pd[p].d.n) / 64 * 64;
-        if (room < qp && room >= 1024) qp = room;
-      } else if (!pl->lds_launch) {
-        // the HBM-only kernel ran 512-query items 9% faster than 2048-query
-        // ones on 40k-feature images; in the staging kernel's launch the
-        // smaller items were slower
-        qp = std::min(qp, kHbmItemQueries);
+  {
+    const std::vector<PairDev>& pd = fp;  // the query-major pairs come first
+    const int P = (int)qm_idx.size();
+    if (mode == CHM_MATCH_PLAIN) {
+      const int qp = pl->tun.wg_threads;
+      pl->pair_begin.resize(P);
+      pl->pair_count.resize(P);
+      pl->pair_lds.resize(P);
+      for (int p = 0; p < P; ++p) {
+        const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+        pl->pair_begin[p] = (int)items.size();
+        for (int q0 = 0; q0 < pd[p].q.n; q0 += qp)
+          items.push_back({p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0});
+        pl->pair_count[p] = (int)items.size() - pl->pair_begin[p];
+        pl->pair_lds[p] = lds;
       }
-      for (int q0 = 0; q0 < pd[p].q.n; q0 += qp) {
-        WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0};
-        const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
-        groups[pd[p].d.codes].push_back({cost, w});
+    } else {
+      // All items go to one persistent launch: the LDS-staging kernel when any
+      // db image fits the code stage (it reads larger ones from HBM in the same
+      // launch), else the HBM-only kernel.  Items are dealt into one bin per
+      // XCD, whole db images at a time (largest total first onto the least
+      // loaded bin), so the work-groups of an XCD share the db images' codes,
+      // members and descriptors in their L2; inside a bin, a db image's items
+      // are consecutive, longest first.
+      const int qpi = pl->tun.queries_per_item;
+      const int nbins = std::max(1, S->n_xcd);
+      std::map<const void*, std::vector<std::pair<double, WorkItem>>> groups;
+      for (int p = 0; p < P; ++p) pl->lds_launch |= ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+      for (int p = 0; p < P; ++p) {
+        const bool lds = ldsmax > 0 && pd[p].d.n <= ldsmax && pd[p].d.n > 0;
+        // Above a large stage an item's sort order may not fit: such pairs
+        // take items small enough to sort, down to one query per thread of a
+        // 1024-thread work-group; below that they keep full items, unsorted.
+        // A launch without any staged pair takes items of at most
+        // tuning.hbm_item_queries queries.
+        int qp = qpi;
+        if (lds) {
+          const int room = lds_sort_room(S->lds_top, pd[p].d.n) / 64 * 64;
+          if (room < qp && room >= 1024) qp = room;
+        } else if (!pl->lds_launch) {
+          // the HBM-only kernel ran 512-query items 9% faster than 2048-query
+          // ones on 40k-feature images; in the staging kernel's launch the
+          // smaller items were slower
+          qp = std::min(qp, pl->tun.hbm_item_queries);
+        }
+        for (int q0 = 0; q0 < pd[p].q.n; q0 += qp) {
+          WorkItem w{p, q0, std::min(pd[p].q.n, q0 + qp), lds ? 1 : 0};
+          const double cost = (double)(w.q1 - w.q0) * (double)(pd[p].d.n + 64);
+          groups[pd[p].d.codes].push_back({cost, w});
+        }
       }
-    }
-    std::vector<std::pair<double, std::vector<std::pair<double, WorkItem>>*>> order;
-    for (auto& g : groups) {
-      double c = 0;
-      for (auto& x : g.second) c += x.first;
-      std::sort(g.second.begin(), g.second.end(),
-                [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
-                  if (x.first != y.first) return x.first > y.first;
-                  if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
-                  return x.second.q0 < y.second.q0;
-                });
-      order.push_back({c, &g.second});
-    }
-    std::stable_sort(order.begin(), order.end(),
-                     [](const auto& x, const auto& y) { return x.first > y.first; });
-    std::vector<std::vector<WorkItem>> bins(nbins);
-    std::vector<double> load(nbins, 0.0);
-    for (auto& g : order) {
-      const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
-      load[b] += g.first;
-      for (auto& x : *g.second) bins[b].push_back(x.second);
-    }
-    // The items that make up the last kTailPercent of a bin's cost are cut
-    // into kTailPieces pieces (whole wavefront chunks), so that the
-    // work-groups draining the bins finish within a smaller item of each
-    // other rather than a full one.
-    for (int b = 0; b < nbins && kTailPercent > 0; ++b) {
-      std::vector<WorkItem>& v = bins[b];
-      auto cost = [&](const WorkItem& w) { return (double)(w.q1 - w.q0) * (double)(pd[w.pair].d.n + 64); };
-      double total = 0, tail = 0;
-      for (const WorkItem& w : v) total += cost(w);
-      size_t cut = v.size();
-      while (cut > 0 && tail < total * kTailPercent / 100.0) tail += cost(v[--cut]);
-      std::vector<WorkItem> out(v.begin(), v.begin() + cut);
-      for (size_t i = cut; i < v.size(); ++i) {
-        const WorkItem& w = v[i];
-        const int piece = std::max(64, ((w.q1 - w.q0 + kTailPieces - 1) / kTailPieces + 63) / 64 * 64);
-        for (int q0 = w.q0; q0 < w.q1; q0 += piece) out.push_back({w.pair, q0, std::min(w.q1, q0 + piece), w.lds});
+      std::vector<std::pair<double, std::vector<std::pair<double, WorkItem>>*>> order;
+      for (auto& g : groups) {
+        double c = 0;
+        for (auto& x : g.second) c += x.first;
+        std::sort(g.second.begin(), g.second.end(),
+                  [](const std::pair<double, WorkItem>& x, const std::pair<double, WorkItem>& y) {
+                    if (x.first != y.first) return x.first > y.first;
+                    if (x.second.pair != y.second.pair) return x.second.pair < y.second.pair;
+                    return x.second.q0 < y.second.q0;
+                  });
+        order.push_back({c, &g.second});
       }
-      v.swap(out);
+      std::stable_sort(order.begin(), order.end(),
+                       [](const auto& x, const auto& y) { return x.first > y.first; });
+      std::vector<std::vector<WorkItem>> bins(nbins);
+      std::vector<double> load(nbins, 0.0);
+      for (auto& g : order) {
+        const int b = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+        load[b] += g.first;
+        for (auto& x : *g.second) bins[b].push_back(x.second);
+      }
+      // The items that make up the last tail_percent of a bin's cost are cut
+      // into kTailPieces pieces (whole wavefront chunks), so that the
+      // work-groups draining the bins finish within a smaller item of each
+      // other rather than a full one.
+      const int tail_pct = pl->tun.tail_percent;
+      for (int b = 0; b < nbins && tail_pct > 0; ++b) {
+        std::vector<WorkItem>& v = bins[b];
+        auto cost = [&](const WorkItem& w) { return (double)(w.q1 - w.q0) * (double)(pd[w.pair].d.n + 64); };
+        double total = 0, tail = 0;
+        for (const WorkItem& w : v) total += cost(w);
+        size_t cut = v.size();
+        while (cut > 0 && tail < total * tail_pct / 100.0) tail += cost(v[--cut]);
+        std::vector<WorkItem> out(v.begin(), v.begin() + cut);
+        for (size_t i = cut; i < v.size(); ++i) {
+          const WorkItem& w = v[i];
+          const int piece = std::max(64, ((w.q1 - w.q0 + kTailPieces - 1) / kTailPieces + 63) / 64 * 64);
+          for (int q0 = w.q0; q0 < w.q1; q0 += piece) out.push_back({w.pair, q0, std::min(w.q1, q0 + piece), w.lds});
+        }
+        v.swap(out);
+      }
+      pl->bins[0] = 0;
+      for (int b = 0; b < nbins; ++b) {
+        items.insert(items.end(), bins[b].begin(), bins[b].end());
+        pl->bins[b + 1] = (int32_t)items.size();
+      }
+      pl->n_bins = nbins;
     }
-    pl->bins[0] = 0;
-    for (int b = 0; b < nbins; ++b) {
-      items.insert(items.end(), bins[b].begin(), bins[b].end());
-      pl->bins[b + 1] = (int32_t)items.size();
-    }
-    pl->n_bins = nbins;
   }
   pl->n_items = (int)items.size();
+  pl->bm = !bm_idx.empty();
+  pl->bm_groups = bp.groups;
+  pl->bm_rounds = bp.rounds;
 
   const uint64_t pairs_bytes = round_up(sizeof(PairDev) * (size_t)std::max(P, 1), 256);
   const uint64_t items_bytes = round_up(sizeof(WorkItem) * (size_t)std::max(pl->n_items, 1), 256);
   const uint64_t queue_bytes = 256;  // kMaxBins counters
   const uint64_t bins_bytes = 256;   // kMaxBins + 1 item offsets
+  const uint64_t ints_bytes = round_up(4 * std::max<size_t>(bp.ints.size(), 1), 256);
   static_assert(kMaxBins * 4 <= 256 && (kMaxBins + 1) * 4 <= 256, "plan tail");
-  pl->mem_bytes = pairs_bytes + items_bytes + queue_bytes + bins_bytes;
+  pl->mem_bytes = pairs_bytes + items_bytes + queue_bytes + bins_bytes + ints_bytes;
   if (!S->arena.alloc(pl->mem_bytes, &pl->mem_off)) {
+    if (pl->state_bytes) S->arena.release(pl->state_off, pl->state_bytes);
     delete pl;
     return fail(CHM_E_CAPACITY, "arena cannot hold the plan's work list (%llu bytes)",
                 (unsigned long long)pl->mem_bytes);
@@ -689,10 +875,12 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   pl->dItems = (WorkItem*)(S->base + pl->mem_off + pairs_bytes);
   pl->dQueue = (uint32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes);
   pl->dBins = (int32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes + queue_bytes);
+  pl->dBmInts = (int32_t*)(S->base + pl->mem_off + pairs_bytes + items_bytes + queue_bytes + bins_bytes);
   // the plan owns the host sources of its upload (and its bin table), so the
   // copies may still be in flight when this call returns
-  pl->h_pairs = std::move(pd);
+  pl->h_pairs = std::move(fp);
   pl->h_items = std::move(items);
+  pl->h_bm_ints = std::move(bp.ints);
   hipStream_t s = (hipStream_t)stream;
   pl->upload_stream = s;
   pl->upload_pending = true;
@@ -702,14 +890,15 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
     e = hipMemcpyAsync(pl->dItems, pl->h_items.data(), sizeof(WorkItem) * pl->n_items, hipMemcpyHostToDevice,
                        s);
   if (e == hipSuccess) e = hipMemcpyAsync(pl->dBins, pl->bins, sizeof pl->bins, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess && !pl->h_bm_ints.empty())
+    e = hipMemcpyAsync(pl->dBmInts, pl->h_bm_ints.data(), 4 * pl->h_bm_ints.size(), hipMemcpyHostToDevice, s);
   if (e == hipSuccess && wait_upload) {
     e = hipStreamSynchronize(s);
     pl->upload_pending = false;
   }
   if (e != hipSuccess) {
     (void)hipStreamSynchronize(s);
-    S->arena.release(pl->mem_off, pl->mem_bytes);
-    delete pl;
+    plan_free(pl);
     return fail(CHM_E_HIP, "plan upload failed: %s", hipGetErrorString(e));
   }
 
@@ -733,19 +922,47 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
   a.lds_max_feats = ldsmax;
   a.lds_top = S->lds_top;
 
-  if (mode == CHM_MATCH_BATCHED && pl->n_items > 0) {
+  if (mode == CHM_MATCH_BATCHED && (pl->n_items > 0 || pl->bm_groups > 0)) {
+    // one graph: the query-major persistent launch (its queue counters reset
+    // by a fill kernel), then the bucket-major launches, table by table and
+    // round by round
     hipStream_t cs = S->cap_stream;
     e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-    if (e == hipSuccess) e = launch_fill_u32(pl->dQueue, 0u, kMaxBins, cs);
-    if (e == hipSuccess) {
-      MatchArgs x = a;
-      x.n_items = pl->n_items;
-      x.n_bins = pl->n_bins;
-      // the LDS stage allows one work-group per CU
-      const int per_cu = pl->lds_launch ? 1 : pl->tun.grid_per_cu;
-      if (!pl->lds_launch) x.lds_max_feats = 0;
-      const int grid = std::min(pl->n_items, S->n_cu * per_cu);
-      e = launch_match(x, a.K, pl->tun.wg_threads, pl->lds_launch, true, grid, cs);
+    if (e == hipSuccess && pl->n_items > 0) {
+      e = launch_fill_u32(pl->dQueue, 0u, kMaxBins, cs);
+      if (e == hipSuccess) {
+        MatchArgs x = a;
+        x.n_items = pl->n_items;
+        x.n_bins = pl->n_bins;
+        // the LDS stage allows one work-group per CU
+        const int per_cu = pl->lds_launch ? 1 : pl->tun.grid_per_cu;
+        if (!pl->lds_launch) x.lds_max_feats = 0;
+        const int grid = std::min(pl->n_items, S->n_cu * per_cu);
+        e = launch_match(x, a.K, pl->tun.wg_threads, pl->lds_launch, true, grid, cs);
+      }
+    }
+    const int nbins = std::max(1, S->n_xcd);
+    for (size_t r = 0; r < pl->bm_rounds.size() && e == hipSuccess; ++r) {
+      BmArgs b;
+      b.pairs = pl->dPairs;
+      b.groups = pl->dBmInts;
+      b.bin_begin = pl->dBmInts + pl->bm_rounds[r].begin_off;
+      b.bin_groups = pl->dBmInts + pl->bm_rounds[r].list_off;
+      b.state = pl->dState;
+      b.out = d_out;
+      b.topk = d_topk;
+      b.n_bins = nbins;
+      b.L = a.L;
+      b.nb = a.nb;
+      b.K = a.K;
+      b.ratio_num = a.ratio_num;
+      b.ratio_den = a.ratio_den;
+      b.accept_single = a.accept_single;
+      const int grid = nbins * pl->bm_rounds[r].max_groups * S->nb;
+      for (int t = 0; t < a.L && e == hipSuccess; ++t) {
+        b.t = t;
+        e = launch_match_bm(b, a.K, grid, cs);
+      }
     }
     hipGraph_t g = nullptr;
     hipError_t e2 = hipStreamEndCapture(cs, &g);
@@ -754,8 +971,7 @@ chm_status chm::plan_build(chm_store* S, const int32_t* h_pairs, int32_t P, cons
     if (g) (void)hipGraphDestroy(g);
     if (e != hipSuccess) {
       if (pl->upload_pending) (void)hipStreamSynchronize(s);
-      S->arena.release(pl->mem_off, pl->mem_bytes);
-      delete pl;
+      plan_free(pl);
       return fail(CHM_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
     }
   }
@@ -795,7 +1011,7 @@ extern "C" chm_status chm_plan_execute(chm_plan* pl, void* stream) {
   hipStream_t s = (hipStream_t)stream;
   pl->last_stream = s;
   pl->executed = true;
-  if (pl->n_items == 0) return CHM_OK;
+  if (pl->n_items == 0 && pl->bm_groups == 0) return CHM_OK;
   if (pl->mode == CHM_MATCH_BATCHED) {
     HIPCHK(hipGraphLaunch(pl->exec, s));
     return CHM_OK;
@@ -815,6 +1031,7 @@ void chm::plan_free(chm_plan* pl) {
   if (!pl) return;
   if (pl->exec) (void)hipGraphExecDestroy(pl->exec);
   pl->st->arena.release(pl->mem_off, pl->mem_bytes);
+  if (pl->state_bytes) pl->st->arena.release(pl->state_off, pl->state_bytes);
   delete pl;
 }
 

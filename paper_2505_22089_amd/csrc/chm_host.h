@@ -86,6 +86,21 @@ struct chm_plan {
   // waited for keeps them until the upload stream has passed it.
   std::vector<chm::PairDev> h_pairs;
   std::vector<chm::WorkItem> h_items;
+  // Bucket-major batched plans: the pairs in group order, the group ranges
+  // and every round's bin tables in one int32 array, and a separate arena
+  // block for the kept lists (reused by each round).
+  bool bm = false;
+  struct BmRound {
+    int begin_off;   // int32 index of the round's n_bins + 1 bin offsets
+    int list_off;    // int32 index of its group list
+    int max_groups;  // groups of its fullest bin
+  };
+  std::vector<BmRound> bm_rounds;
+  std::vector<int32_t> h_bm_ints;
+  int bm_groups = 0;
+  int32_t* dBmInts = nullptr;
+  uint32_t* dState = nullptr;
+  uint64_t state_off = 0, state_bytes = 0;
   hipStream_t upload_stream = nullptr;
   bool upload_pending = false;
 };

@@ -19,18 +19,21 @@ struct ImageDev {
   const uint8_t* ids;       // L x n_pad: bucket id of each descriptor, table-major
   const uint32_t* norms;    // n: squared L2 norm
   const int32_t* offsets;   // L x (nb + 1): padded bucket ranges, multiples of 8
+  const int32_t* counts;    // L x nb: members of each bucket (without its pads)
   const uint32_t* members;  // L x m_stride code byte offsets (16 j), ascending inside each
                             // bucket, then pads
   const uint4* tcodes;      // L x m_stride codes in bucket order, or null (small images)
   int32_t n;
   int32_t n_pad;
   int32_t m_stride;         // members per table: n + 7 * min(nb, n), rounded up to 8
+  int32_t reserved;
 };
 
 struct PairDev {
   ImageDev q;
   ImageDev d;
   int64_t out_off;
+  int64_t st_off;           // bucket-major plans: first state row of the pair in its round
 };
 
 struct WorkItem {
@@ -64,6 +67,30 @@ struct MatchArgs {
   int32_t whole_bucket;   // re-rank every candidate as close as the K-th
   int32_t lds_max_feats;  // capacity of the LDS code stage (0 = none)
   int32_t lds_top;        // LDS-staging launches: byte address of the control words
+};
+
+// Bucket-major matching (match_bm.hip): one launch per table and round.
+// Pairs are ordered so that each group (pairs[groups[g] .. groups[g+1]))
+// shares one db image; bin x of the launch holds the groups
+// bin_groups[bin_begin[x] .. bin_begin[x+1]), and work-group x + n_bins * k
+// takes bucket k % nb of the bin's (k / nb)-th group.  state holds KT keys
+// per (pair, query) at row pairs[p].st_off + query.
+struct BmArgs {
+  const PairDev* pairs;
+  const int32_t* groups;
+  const int32_t* bin_groups;
+  const int32_t* bin_begin;
+  uint32_t* state;
+  int32_t* out;
+  uint32_t* topk;
+  int32_t n_bins;
+  int32_t t;              // table of this launch
+  int32_t L;
+  int32_t nb;             // 2^m
+  int32_t K;
+  int32_t ratio_num;
+  int32_t ratio_den;
+  int32_t accept_single;
 };
 
 // Device SAO (sao_device.hip).  h_starts[p] is where pair p's query rows
@@ -111,12 +138,12 @@ __host__ __device__ constexpr int lds_sort_room(int lds_top, int n) { return (ld
 // Sections of one image slot in the arena (byte offsets from the slot
 // start, each 256-byte aligned): descriptors n x 128, long codes n x 16,
 // bucket ids L x n_pad, squared norms n x 4, offsets L x (2^m + 1) int32,
-// members L x m_stride u32, and for images too large for the LDS code stage
+// real member counts L x 2^m int32, members L x m_stride u32, and for images too large for the LDS code stage
 // the codes again in bucket order, L x m_stride x 16 (tcodes[t][pos] is the
 // code of members[t][pos]).  Used by the host to size and address slots and
 // by the hashing kernels to address a slot from its base alone.
 struct ImageLayout {
-  uint64_t desc, codes, ids, norms, offsets, members, tcodes, total;
+  uint64_t desc, codes, ids, norms, offsets, counts, members, tcodes, total;
   int n_pad;
   int m_stride;
   bool has_tcodes;
@@ -137,6 +164,7 @@ __host__ __device__ inline ImageLayout image_layout(int L, int m, int n) {
   l.ids = o;     o += layout_round((uint64_t)L * l.n_pad, 256);
   l.norms = o;   o += layout_round((uint64_t)n * 4, 256);
   l.offsets = o; o += layout_round((uint64_t)L * (nb + 1) * 4, 256);
+  l.counts = o;  o += layout_round((uint64_t)L * nb * 4, 256);
   l.members = o; o += layout_round((uint64_t)L * l.m_stride * 4, 256);
   l.has_tcodes = n > lds_code_cap();
   l.tcodes = o;  o += l.has_tcodes ? layout_round((uint64_t)L * l.m_stride * 16, 256) : 0;
@@ -161,6 +189,7 @@ struct HashImage {
   uint8_t* ids;             // L x n_pad, table-major
   uint32_t* norms;
   int32_t* offsets;
+  int32_t* counts;          // L x nb members per bucket, without pads
   uint32_t* members;        // 16 * db index (the byte offset of its code)
   uint4* tcodes;            // codes in bucket order, or null
   int32_t n;
@@ -184,6 +213,7 @@ __host__ __device__ inline HashImage hash_image(const HashSlot& s, int L, int m)
   h.ids = s.base + l.ids;
   h.norms = reinterpret_cast<uint32_t*>(s.base + l.norms);
   h.offsets = reinterpret_cast<int32_t*>(s.base + l.offsets);
+  h.counts = reinterpret_cast<int32_t*>(s.base + l.counts);
   h.members = reinterpret_cast<uint32_t*>(s.base + l.members);
   h.tcodes = l.has_tcodes ? reinterpret_cast<uint4*>(s.base + l.tcodes) : nullptr;
   h.n = s.n;
@@ -222,6 +252,9 @@ hipError_t launch_buckets(const HashBatch& hb, hipStream_t s);
 hipError_t launch_match(const MatchArgs& a, int K, int wg, bool lds, bool persistent, int grid,
                         hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);
+// Table a.t of a bucket-major round over `grid` work-groups (n_bins x the
+// largest bin's groups x nb).
+hipError_t launch_match_bm(const BmArgs& a, int K, int grid, hipStream_t s);
 
 hipError_t launch_bruteforce(const uint8_t* q, int nq, const uint8_t* d, int nd, int ra, int rb,
                              int32_t* out, void* work, int splits, hipStream_t s);

@@ -3,9 +3,11 @@ the benchmark times.
 
 * knn-50x8000 (the benchmark workload): every output of all 400 pairs;
 * strips (500 images, 2k-20k features) and knn-200x40000: every pair matched
-  on the GPU, sampled pairs against the oracle (the largest and smallest db
-  images, so both the LDS-staged and the global-memory match paths, plus
-  random ones);
+  on the GPU and compared with the oracle's stored per-pair digests
+  (tests/golden/make_digests.py; both the LDS-staged and the global-memory
+  match paths occur);
+* a 1,200-image grid of 10,000-feature images, every pair against stored
+  digests;
 * a grid view graph run end to end through an MBR schedule whose residency
   cap binds (images loaded and evicted between block rows), every output
   against the oracle.
@@ -19,6 +21,7 @@ from paper_2505_22089_amd import chm, synth
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 from tests.gpu_helpers import device, gpu_arrays, load_all, new_store, run_match  # noqa: E402
+from tests.digests import load_golden, match_counts, pair_digests  # noqa: E402
 
 
 def oracle_slices(wl, pairs):
@@ -31,15 +34,6 @@ def oracle_slices(wl, pairs):
 
 def gpu_slices(out, offs, idx):
     return [out[offs[p]:offs[p + 1]] for p in idx]
-
-
-def sample_pairs(wl, n_each, seed):
-    rng = np.random.default_rng(seed)
-    nd = np.array([wl.images[d].shape[0] for d in wl.pairs[:, 1]])
-    order = np.argsort(nd, kind="stable")
-    idx = set(order[:n_each].tolist()) | set(order[-n_each:].tolist())
-    idx |= set(rng.choice(len(wl.pairs), n_each, replace=False).tolist())
-    return sorted(idx)
 
 
 def test_knn_50x8000_all_pairs():
@@ -55,37 +49,62 @@ def test_knn_50x8000_all_pairs():
     ref, roffs, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
     assert np.array_equal(offs, roffs)
     assert np.array_equal(out, ref)
-    # other launch shapes (HBM-only codes, small work-groups) and the plain path agree
+    # the query-major kernel (LDS-staged codes, then HBM-only codes, small
+    # work-groups), bucket-major groups of one pair and the plain path agree
+    st.set_tuning(match_kernel=chm.KERNEL_QUERY_MAJOR)
+    assert np.array_equal(run_match(st, wl.pairs)[0], ref)
     st.set_tuning(queries_per_item=1024, wg_threads=1024, lds_codes=0, grid_per_cu=2)
+    assert np.array_equal(run_match(st, wl.pairs)[0], ref)
+    st.set_tuning(match_kernel=chm.KERNEL_BUCKET_MAJOR, bm_min_db_feats=0)
+    assert np.array_equal(run_match(st, wl.pairs)[0], ref)
+    st.set_tuning(group_queries=1)
     assert np.array_equal(run_match(st, wl.pairs)[0], ref)
     st.set_tuning(wg_threads=256, lds_codes=0)
     assert np.array_equal(run_match(st, wl.pairs, mode=chm.MATCH_PLAIN)[0], ref)
     st.close()
 
 
-def test_strips_sampled_pairs():
+def check_all_pairs_against_digests(wl, name, out, offs):
+    """Every pair's GPU matches against the oracle's stored per-pair digest
+    (tests/golden/make_digests.py).  On a mismatch the oracle recomputes the
+    first few differing pairs, so the failure says whether the GPU or a stale
+    golden file is wrong."""
+    dig, cnt, pairs, meta = load_golden(name)
+    assert np.array_equal(pairs, wl.pairs), "golden pair list of %s does not match the generator" % name
+    assert (int(meta["L"]), int(meta["m"]), int(meta["K"])) == (wl.L, wl.m, wl.K)
+    got = pair_digests(out, offs)
+    bad = np.nonzero(got != dig)[0]
+    if len(bad):
+        idx = bad[:3].tolist()
+        ref = oracle_slices(wl, wl.pairs[idx])
+        diffs = ["pair %d %s: %d outputs differ from the oracle, GPU matches %d, stored count %d"
+                 % (p, wl.pairs[p].tolist(), int((g != r).sum()), int((g >= 0).sum()), int(cnt[p]))
+                 for p, g, r in zip(idx, gpu_slices(out, offs, idx), ref)]
+        raise AssertionError("%d of %d pairs differ from the stored oracle digests; %s"
+                             % (len(bad), len(dig), "; ".join(diffs)))
+    assert np.array_equal(match_counts(out, offs), cnt)
+
+
+def test_strips_all_pairs():
+    """All 5,554 pairs of the strips workload (500 images, 2k-20k features)."""
     wl = synth.config3()
     st = new_store(wl)
     load_all(st, wl.images)
     nd = np.array([x.shape[0] for x in wl.images])
     assert nd.min() < 10175 < nd.max()  # LDS-staged and global-memory db images both occur
     out, _, offs = run_match(st, wl.pairs)
-    idx = sample_pairs(wl, 8, seed=3)
-    ref = oracle_slices(wl, wl.pairs[idx])
-    for k, (g, r) in enumerate(zip(gpu_slices(out, offs, idx), ref)):
-        assert np.array_equal(g, r), "pair %d %s" % (idx[k], wl.pairs[idx[k]])
+    check_all_pairs_against_digests(wl, "strips", out, offs)
     st.close()
 
 
-def test_knn_200x40000_sampled_pairs():
+def test_knn_200x40000_all_pairs():
+    """All 2,000 pairs of 200 images x 40,000 features, BF16 projection; then
+    the FP32 projection gives the same codes and bucket ids."""
     wl = synth.config4()
     st = new_store(wl)
     load_all(st, wl.images)
     out, _, offs = run_match(st, wl.pairs)
-    idx = sorted(np.random.default_rng(4).choice(len(wl.pairs), 3, replace=False).tolist())
-    ref = oracle_slices(wl, wl.pairs[idx])
-    for k, (g, r) in enumerate(zip(gpu_slices(out, offs, idx), ref)):
-        assert np.array_equal(g, r), "pair %d %s" % (idx[k], wl.pairs[idx[k]])
+    check_all_pairs_against_digests(wl, "knn-200x40000", out, offs)
 
     # FP32 projection gives the same codes
     st.close()
@@ -98,6 +117,19 @@ def test_knn_200x40000_sampled_pairs():
         ref_h = O.hash_image(wl.images[i], wl.W, wl.mu, wl.L, wl.m)
         assert np.array_equal(g["codes"], ref_h.codes) and np.array_equal(g["ids"], ref_h.ids)
     st32.close()
+
+
+def test_grid_1200x10000_all_pairs():
+    """A 12 x 100 grid of 10,000-feature images (the grid workload's image
+    size and view-graph shape on 1,200 of its 5,000 images), all pairs in one
+    batched plan, every pair against the stored oracle digests.  The full
+    5,000-image grid is compared pair by pair in the benchmark's grid job."""
+    wl = synth.config5(rows=12, cols=100)
+    st = new_store(wl)
+    load_all(st, wl.images)
+    out, _, offs = run_match(st, wl.pairs)
+    check_all_pairs_against_digests(wl, "grid-1200x10000", out, offs)
+    st.close()
 
 
 @pytest.mark.parametrize("slack_caps", [0, 0.03, 0.1, 1])
@@ -157,6 +189,11 @@ def test_db_images_around_the_lds_stage_limits():
     st = new_store(wl)
     load_all(st, wl.images)
     ref = oracle_slices(wl, wl.pairs)
+    st.set_tuning(bm_min_db_feats=0)
+    out, _, offs = run_match(st, wl.pairs)  # bucket major for every pair
+    for p in range(len(wl.pairs)):
+        assert np.array_equal(out[offs[p]:offs[p + 1]], ref[p]), ("bucket major", p, wl.pairs[p])
+    st.set_tuning(match_kernel=chm.KERNEL_QUERY_MAJOR)
     for tuning in ((3072, 1024, 1, 1), (2048, 1024, 1, 1), (512, 1024, 1, 1), (1536, 1024, 1, 1)):
         st.set_tuning(*tuning)
         out, _, offs = run_match(st, wl.pairs)

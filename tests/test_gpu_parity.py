@@ -107,6 +107,22 @@ def test_hash_parity_near_hyperplane_descriptors():
 
 
 def check_matches(st, wl, pairs, mode, K):
+    """Matches and top-K keys of the pairs against the oracle; a batched
+    plan is checked with both match kernels (bucket major, then query major)."""
+    if mode == chm.MATCH_BATCHED:
+        out = None
+        kernel = st.tuning_dict()
+        for k in (chm.KERNEL_BUCKET_MAJOR, chm.KERNEL_QUERY_MAJOR):
+            st.set_tuning(match_kernel=k, bm_min_db_feats=0)
+            o = check_matches_once(st, wl, pairs, mode, K)
+            assert out is None or np.array_equal(o, out)
+            out = o
+        st.set_tuning(**kernel)
+        return out
+    return check_matches_once(st, wl, pairs, mode, K)
+
+
+def check_matches_once(st, wl, pairs, mode, K):
     out, topk, offs = run_match(st, pairs, mode, want_topk=True)
     H = {}
     for p, (q, d) in enumerate(pairs):
@@ -224,12 +240,31 @@ def test_match_parity_lds_and_global_paths():
     load_all(st, wl.images)
     pairs = [(1, 0), (2, 0), (0, 1), (3, 1), (1, 3), (2, 3)]
     ref = check_matches(st, wl, pairs, chm.MATCH_BATCHED, 8)
-    for tun in (dict(lds_codes=0), dict(wg_threads=256), dict(queries_per_item=64),
-                dict(queries_per_item=4096, grid_per_cu=1)):
+    for tun in (dict(match_kernel=chm.KERNEL_QUERY_MAJOR), dict(lds_codes=0), dict(wg_threads=256),
+                dict(queries_per_item=64), dict(queries_per_item=4096, grid_per_cu=1),
+                dict(match_kernel=chm.KERNEL_BUCKET_MAJOR, group_queries=1, bm_min_db_feats=0),
+                dict(bm_min_db_feats=10176)):
         st.set_tuning(**tun)
         for mode in (chm.MATCH_BATCHED, chm.MATCH_PLAIN):
             out, _, _ = run_match(st, pairs, mode)
             assert np.array_equal(out, ref), "tuning %s mode %d" % (tun, mode)
+
+
+@pytest.mark.parametrize("K", [2, 8])
+def test_bucket_major_rounds(K):
+    """Bucket-major plans whose kept lists do not fit the arena at once run
+    in several rounds that reuse one state block; groups of several pairs
+    share a db image (and empty images and self pairs occur).  Every round's
+    output equals the oracle and the query-major kernel."""
+    wl = small_workload([3000, 2500, 3100, 0, 2900, 1, 2700], seed=17, copies=0.4)
+    pairs = [(q, d) for d in range(7) for q in range(7) if q != d and abs(q - d) <= 3] + [(4, 4)]
+    st = new_store(wl, K=K, extra=1200 << 10)
+    load_all(st, wl.images)
+    ref = check_matches(st, wl, pairs, chm.MATCH_BATCHED, K)
+    for gq in (1, 6000, 1 << 20):
+        st.set_tuning(match_kernel=chm.KERNEL_BUCKET_MAJOR, group_queries=gq, bm_min_db_feats=0)
+        assert np.array_equal(run_match(st, pairs)[0], ref), gq
+    st.close()
 
 
 def test_match_duplicates_and_degenerate():

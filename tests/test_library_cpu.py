@@ -43,7 +43,7 @@ def test_library_targets_gfx950_only():
 def test_config_defaults_and_validation():
     c = chm.config()
     assert (c.num_tables, c.bucket_bits, c.top_k, c.ratio_num, c.ratio_den) == (6, 8, 8, 4, 5)
-    assert c.abi_version == chm.ABI_VERSION and chm.lib().chm_abi_version() == 1
+    assert c.abi_version == chm.ABI_VERSION and chm.lib().chm_abi_version() == 2
     assert chm.image_bytes(c, 0) > 0
     b8000 = chm.image_bytes(c, 8000)
     assert b8000 >= 8000 * (128 + 16 + 6 + 4 + 12)   # desc, code, L ids, norm, L u16 members
