@@ -287,6 +287,20 @@ chm_status chm_bruteforce(const uint8_t *d_q, int32_t nq, const uint8_t *d_d, in
                           int32_t ratio_num, int32_t ratio_den, int32_t *d_out, void *d_work,
                           uint64_t work_bytes, void *stream);
 
+/* chm_bruteforce for callers that cannot allocate device memory (code under
+ * HIP graph capture, serving loops, harnesses that forbid hipMalloc): the
+ * same computation and output, with the workspace taken from a fixed
+ * 32 MiB device array the library holds on each GPU (until the process
+ * ends) instead of a caller buffer.  It allocates nothing and calls no
+ * hipMalloc/hipFree.  Sizes whose chm_bruteforce_work_bytes exceed 32 MiB
+ * (about 2 million queries at one db split; a 40,000 x 40,000 pair needs
+ * 4.5 MB) are rejected with CHM_E_CAPACITY.  All calls on one GPU share that
+ * array: calls that overlap in time on one GPU (other streams, other host
+ * threads) race and give undefined results; calls ordered on one stream are
+ * safe.  The first call on a device resolves its copy of the array. */
+chm_status chm_bruteforce_noalloc(const uint8_t *d_q, int32_t nq, const uint8_t *d_d, int32_t nd,
+                                  int32_t ratio_num, int32_t ratio_den, int32_t *d_out, void *stream);
+
 /* ------------------------------------------------------------------ schedule
  * Host-only MBR block schedule (Sec. 2.2 steps (1)-(5), Algorithm 1, GPS of
  * Appendix A).  Usable without a GPU.

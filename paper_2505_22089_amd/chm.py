@@ -67,7 +67,7 @@ EXPORTS = [
     "chm_store_rehash", "chm_store_evict", "chm_store_image_feats", "chm_store_stats",
     "chm_debug_image", "chm_plan_create", "chm_plan_execute", "chm_plan_destroy",
     "chm_match_pairs", "chm_store_get_tuning", "chm_store_set_tuning",
-    "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_schedule_mbr", "chm_schedule_num_steps",
+    "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_bruteforce_noalloc", "chm_schedule_mbr", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
     "chm_run_schedule_sao", "chm_ransac_filter",
@@ -106,6 +106,7 @@ def lib():
             "chm_store_set_tuning": (i32, [vp, P(Tuning)]),
             "chm_bruteforce_work_bytes": (i32, [i32, i32, P(u64)]),
             "chm_bruteforce": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, u64, vp]),
+            "chm_bruteforce_noalloc": (i32, [vp, i32, vp, i32, i32, i32, vp, vp]),
             "chm_schedule_mbr": (i32, [i32, vp, i32, vp, u64, i32, P(vp)]),
             "chm_schedule_num_steps": (i32, [vp]),
             "chm_schedule_step": (i32, [vp, i32, P(P(i32)), P(i32), P(P(i32)), P(i32), P(P(i32)), P(i32)]),
@@ -349,6 +350,12 @@ def bruteforce(q, d, out, work, ratio=(4, 5), stream=None):
     _check(lib().chm_bruteforce(_dev_ptr(q), int(q.shape[0]), _dev_ptr(d), int(d.shape[0]),
                                 int(ratio[0]), int(ratio[1]), _dev_ptr(out), _dev_ptr(work),
                                 work.numel() * work.element_size(), _stream(stream)))
+
+
+def bruteforce_noalloc(q, d, out, ratio=(4, 5), stream=None):
+    """chm_bruteforce with the library's own fixed device workspace."""
+    _check(lib().chm_bruteforce_noalloc(_dev_ptr(q), int(q.shape[0]), _dev_ptr(d), int(d.shape[0]),
+                                        int(ratio[0]), int(ratio[1]), _dev_ptr(out), _stream(stream)))
 
 
 @dataclass

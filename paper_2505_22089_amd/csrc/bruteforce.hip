@@ -18,6 +18,7 @@
 // scores cannot change the output (equal best and second distances fail
 // the ratio test for any t_r <= 1), so which column wins one is immaterial.
 #include <climits>
+#include <mutex>
 
 #include "chm_internal.h"
 
@@ -193,6 +194,33 @@ __global__ void k_bf_merge(const int4* work, int splits, const uint8_t* Q, int n
   // keys back to scores: s = key >> log2 T (arithmetic)
   const int64_t e1 = (int64_t)nrm - (s1 >> kBfShift), e2 = (int64_t)nrm - (s2 >> kBfShift);
   out[i] = ((int64_t)rb * rb * e1 < (int64_t)ra * ra * e2) ? j1 : -1;
+}
+
+// Workspace of chm_bruteforce_noalloc: a file-scope device array, one copy
+// per GPU, holding the per-split partial top-2 of every query (16 B per
+// query and split).  Host code never uses the array's name as an address:
+// bruteforce_scratch() resolves this device's copy once and caches it.
+__device__ __align__(256) uint8_t g_bf_scratch[kBfScratchBytes];
+
+namespace {
+std::mutex g_bf_scratch_mu;
+void* g_bf_scratch_ptr[kBfScratchDevices] = {};
+}  // namespace
+
+hipError_t bruteforce_scratch(void** out) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= kBfScratchDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_bf_scratch_mu);
+  if (!g_bf_scratch_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_bf_scratch));
+    if (e != hipSuccess) return e;
+    g_bf_scratch_ptr[dev] = p;
+  }
+  *out = g_bf_scratch_ptr[dev];
+  return hipSuccess;
 }
 
 int bruteforce_splits(int nq, int nd) {

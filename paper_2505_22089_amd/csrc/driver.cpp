@@ -262,3 +262,27 @@ extern "C" chm_status chm_bruteforce(const uint8_t* d_q, int32_t nq, const uint8
   if (e != hipSuccess) return fail(CHM_E_HIP, "brute force launch failed: %s", hipGetErrorString(e));
   return CHM_OK;
 }
+
+extern "C" chm_status chm_bruteforce_noalloc(const uint8_t* d_q, int32_t nq, const uint8_t* d_d, int32_t nd,
+                                             int32_t ra, int32_t rb, int32_t* d_out, void* stream) {
+  clear_error();
+  uint64_t need = 0;
+  chm_status st = chm_bruteforce_work_bytes(nq, nd, &need);
+  if (st) return st;
+  if (need > kBfScratchBytes)
+    return fail(CHM_E_CAPACITY,
+                "brute force of %d x %d descriptors needs %llu bytes of workspace, beyond the %llu-byte "
+                "library workspace (use chm_bruteforce with a caller workspace)",
+                nq, nd, (unsigned long long)need, (unsigned long long)kBfScratchBytes);
+  if (ra <= 0 || rb <= 0 || ra > rb || rb > 46340)
+    return fail(CHM_E_INVALID_ARG, "ratio must satisfy 0 < num <= den <= 46340");
+  if (nq > 0 && (!d_q || !d_out)) return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (nd > 0 && !d_d) return fail(CHM_E_INVALID_ARG, "NULL db descriptors");
+  if (((uintptr_t)d_q | (uintptr_t)d_d) % 16) return fail(CHM_E_INVALID_ARG, "buffers must be 16-byte aligned");
+  void* work = nullptr;
+  hipError_t e = bruteforce_scratch(&work);
+  if (e != hipSuccess) return fail(CHM_E_HIP, "library workspace lookup failed: %s", hipGetErrorString(e));
+  e = launch_bruteforce(d_q, nq, d_d, nd, ra, rb, d_out, work, bruteforce_splits(nq, nd), (hipStream_t)stream);
+  if (e != hipSuccess) return fail(CHM_E_HIP, "brute force launch failed: %s", hipGetErrorString(e));
+  return CHM_OK;
+}
