@@ -3,30 +3,34 @@
 // members, members ascending inside each bucket).
 //
 // A member is stored as 16 j, the byte offset of db point j's long code, so
-// a matching lane addresses the code with no arithmetic.  Images too large
-// for the match kernel's LDS code stage also get their codes copied in
-// bucket order, so that the 8 codes of a block are one contiguous 128
-// bytes.  Each bucket's range of the members array is padded to a multiple
-// of 8 entries with copies of the bucket's first (smallest) member, and
-// starts at a multiple of 8: a matching lane then reads whole aligned
-// 32-byte blocks of 8 members and needs no bounds test per entry (a repeated
-// member is a candidate already seen, which the set semantics of the
-// candidate list drop).
-// offsets[t][b] .. offsets[t][b + 1] is the padded range.
+// a matching lane addresses the code with no arithmetic.  Each bucket's
+// range of the members array is padded to a multiple of 8 entries with
+// copies of the bucket's first (smallest) member, and starts at a multiple
+// of 8: a matching lane then reads whole aligned 32-byte blocks of 8 members
+// and needs no bounds test per entry (a repeated member is a candidate
+// already seen, which the set semantics of the candidate list drop).
+// offsets[t][b] .. offsets[t][b + 1] is the padded range and counts[t][b]
+// the bucket's members without pads.
 //
-// One work-group per (image, table).  The table's ids are staged in LDS once;
-// each wavefront owns a contiguous segment of descriptors.  Pass 1 counts
-// per (wavefront, bucket) and finds each bucket's first member; a scan turns
-// the counts into each wavefront's starting position inside each bucket;
-// pass 2 scatters, ranking equal ids inside a 64-lane chunk by the lanes'
-// bits in a per-wavefront LDS mask of each bucket (each lane ORs its bit in:
-// the rank is the count of lower lanes with the same id), so the order
-// inside a bucket is the descriptor order; the pads are written last.
+// k_buckets: one work-group per (image, table).  The table's ids are staged
+// in LDS once; each wavefront owns a contiguous segment of descriptors.
+// Pass 1 counts per (wavefront, bucket) and finds each bucket's first
+// member; a scan turns the counts into each wavefront's starting position
+// inside each bucket; pass 2 scatters, ranking equal ids inside a 64-lane
+// chunk by the lanes' bits in a per-wavefront LDS mask of each bucket (each
+// lane ORs its bit in: the rank is the count of lower lanes with the same
+// id), so the order inside a bucket is the descriptor order; the pads are
+// written last.
+//
+// k_tcodes: for images too large for the query-major kernel's LDS code
+// stage, the codes again in bucket order (tcodes[t][pos] = codes[j] for
+// members[t][pos] = 16 j), so that a block's 8 codes are one contiguous 128
+// bytes.  Written in order (coalesced), the codes gathered from L2.
 #include "chm_internal.h"
 
 namespace chm {
 
-constexpr int kBucketWG = 1024;
+constexpr int kBucketWG = 512;
 constexpr int kBucketWaves = kBucketWG / 64;
 constexpr int kBucketMaxN = 65536;
 
@@ -56,7 +60,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
 
   const int im = blockIdx.x / hb.L;
   const int t = blockIdx.x % hb.L;
-  const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
+  const HashImage I = hash_image(hb, im);
   const int n = I.n;
   const int nb = 1 << hb.m;
   const int tid = threadIdx.x;
@@ -139,7 +143,6 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   __syncthreads();
 
   uint32_t* mem = I.members + (size_t)t * I.m_stride;
-  uint4* tc = I.tcodes ? I.tcodes + (size_t)t * I.m_stride : nullptr;  // codes in bucket order
   for (int c = c0; c < c1; ++c) {
     const int i = c * 64 + lane;
     const bool valid = i < n;
@@ -147,10 +150,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
     const uint64_t peers = peers_of(peer[wave], b, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt);
     const uint32_t start = valid ? cnt[wave][b] : 0u;
-    if (valid) {
-      mem[start + rank] = 16u * (uint32_t)i;
-      if (tc) tc[start + rank] = I.codes[i];
-    }
+    if (valid) mem[start + rank] = 16u * (uint32_t)i;
     __builtin_amdgcn_wave_barrier();
     if (valid && rank == 0) cnt[wave][b] = start + (uint32_t)__popcll(peers);
     __builtin_amdgcn_wave_barrier();
@@ -158,12 +158,43 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   // pads (positions no scattered member takes) and the unused tail
   for (int b = tid; b < nb; b += kBucketWG) {
     const uint32_t c = real[b], pc = (c + 7u) & ~7u;
-    for (uint32_t k = c; k < pc; ++k) {
-      mem[pbase[b] + k] = 16u * first[b];
-      if (tc) tc[pbase[b] + k] = I.codes[first[b]];
-    }
+    for (uint32_t k = c; k < pc; ++k) mem[pbase[b] + k] = 16u * first[b];
   }
   for (int i = (int)s_total + tid; i < I.m_stride; i += kBucketWG) mem[i] = 0;
+}
+
+// Bucket-ordered code copies.  Work-groups are dealt to the XCDs
+// round-robin; work-group w = x + n_xcd k (XCD x) copies slice k % slices
+// of batch image x + n_xcd (k / slices): entries [s kTcPer, (s + 1) kTcPer)
+// of its L x m_stride.  All slices of an image thus run on one XCD, whose
+// L2 holds the image's codes for the gathers.  Images without a copy, and
+// work-groups past the batch, return at once.  A thread takes 4 consecutive
+// entries: one 16-byte load of their members, 4 code gathers, 4 stores.
+constexpr int kTcWG = 256;
+constexpr int kTcPer = 8192;
+
+__global__ __launch_bounds__(kTcWG) void k_tcodes(HashBatch hb, int slices, int n_xcd) {
+  const int x = (int)(blockIdx.x % (unsigned)n_xcd);
+  const int k = (int)(blockIdx.x / (unsigned)n_xcd);
+  const int im = x + n_xcd * (k / slices);
+  if (im >= hb.count) return;
+  const HashImage I = hash_image(hb, im);
+  if (!I.tcodes) return;
+  const uint32_t total = (uint32_t)hb.L * (uint32_t)I.m_stride;  // a multiple of 8
+  const uint32_t s0 = (uint32_t)(k % slices) * (uint32_t)kTcPer;
+  const uint32_t s1 = min(total, s0 + (uint32_t)kTcPer);
+  const char* codes = reinterpret_cast<const char*>(I.codes);
+  for (uint32_t pos = s0 + 4 * threadIdx.x; pos < s1; pos += 4 * kTcWG) {
+    const uint4 m = *reinterpret_cast<const uint4*>(I.members + pos);
+    const uint4 c0 = *reinterpret_cast<const uint4*>(codes + m.x);
+    const uint4 c1 = *reinterpret_cast<const uint4*>(codes + m.y);
+    const uint4 c2 = *reinterpret_cast<const uint4*>(codes + m.z);
+    const uint4 c3 = *reinterpret_cast<const uint4*>(codes + m.w);
+    I.tcodes[pos] = c0;
+    I.tcodes[pos + 1] = c1;
+    I.tcodes[pos + 2] = c2;
+    I.tcodes[pos + 3] = c3;
+  }
 }
 
 __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
@@ -171,21 +202,28 @@ __global__ void k_fill_u32(uint32_t* p, uint32_t v, int n) {
   if (i < n) p[i] = v;
 }
 
-hipError_t launch_buckets(const HashBatch& hb, hipStream_t s) {
+hipError_t launch_buckets(const HashBatch& hb, int n_xcd, hipStream_t s) {
   if (hb.count == 0) return hipSuccess;
   // LDS for the ids sized to the batch, so that small images leave room for
   // several work-groups per CU
   int n_pad = 8;
   for (int i = 0; i < hb.count; ++i) n_pad = max(n_pad, (hb.img[i].n + 7) / 8 * 8);
   if (n_pad > kBucketMaxN) return hipErrorInvalidValue;
-  static bool attr_set = false;
-  if (!attr_set) {
-    hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_buckets),
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, kBucketMaxN);
-    if (e != hipSuccess) return e;
-    attr_set = true;
-  }
+  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_buckets),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBucketMaxN);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_buckets, dim3(hb.count * hb.L), dim3(kBucketWG), (size_t)n_pad, s, hb);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int slices = 0;
+  for (int i = 0; i < hb.count; ++i) {
+    const ImageLayout l = image_layout(hb.L, hb.m, hb.img[i].n);
+    if (l.has_tcodes) slices = max(slices, (hb.L * l.m_stride + kTcPer - 1) / kTcPer);
+  }
+  if (slices == 0) return hipSuccess;
+  if (n_xcd < 1) n_xcd = 1;
+  const int per_xcd = (hb.count + n_xcd - 1) / n_xcd;
+  hipLaunchKernelGGL(k_tcodes, dim3(n_xcd * per_xcd * slices), dim3(kTcWG), 0, s, hb, slices, n_xcd);
   return hipGetLastError();
 }
 

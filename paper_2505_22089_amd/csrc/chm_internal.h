@@ -173,14 +173,14 @@ __host__ __device__ inline ImageLayout image_layout(int L, int m, int n) {
 }
 
 // Hashing of a batch of images.  The batch is a kernel argument, so it only
-// carries each image's slot base and size (the kernel argument block stays
-// far below 4 KiB); kernels expand an entry with hash_image().
-constexpr int kHashBatch = 64;
+// carries each image's slot (its offset from the arena base in 256-byte
+// units) and size, 8 bytes an image; kernels expand an entry with
+// hash_image().
+constexpr int kHashBatch = 128;
 
 struct HashSlot {
-  uint8_t* base;
+  uint32_t off256;          // slot offset / 256 from HashBatch::arena
   int32_t n;
-  int32_t reserved;
 };
 
 struct HashImage {
@@ -198,28 +198,35 @@ struct HashImage {
 };
 
 struct HashBatch {
+  uint8_t* arena;
   HashSlot img[kHashBatch];
   int32_t tile_prefix[kHashBatch + 1];  // 32-descriptor tiles before image i
   int32_t count;
   int32_t L;
   int32_t m;
+  uint32_t seq;             // the store's batch number (nonzero): the fix-up
+                            // list's overflow word holds it when this batch overflowed
 };
 
-__host__ __device__ inline HashImage hash_image(const HashSlot& s, int L, int m) {
-  const ImageLayout l = image_layout(L, m, s.n);
+__host__ __device__ inline HashImage hash_image_at(uint8_t* base, int n, int L, int m) {
+  const ImageLayout l = image_layout(L, m, n);
   HashImage h;
-  h.desc = s.base + l.desc;
-  h.codes = reinterpret_cast<uint4*>(s.base + l.codes);
-  h.ids = s.base + l.ids;
-  h.norms = reinterpret_cast<uint32_t*>(s.base + l.norms);
-  h.offsets = reinterpret_cast<int32_t*>(s.base + l.offsets);
-  h.counts = reinterpret_cast<int32_t*>(s.base + l.counts);
-  h.members = reinterpret_cast<uint32_t*>(s.base + l.members);
-  h.tcodes = l.has_tcodes ? reinterpret_cast<uint4*>(s.base + l.tcodes) : nullptr;
-  h.n = s.n;
+  h.desc = base + l.desc;
+  h.codes = reinterpret_cast<uint4*>(base + l.codes);
+  h.ids = base + l.ids;
+  h.norms = reinterpret_cast<uint32_t*>(base + l.norms);
+  h.offsets = reinterpret_cast<int32_t*>(base + l.offsets);
+  h.counts = reinterpret_cast<int32_t*>(base + l.counts);
+  h.members = reinterpret_cast<uint32_t*>(base + l.members);
+  h.tcodes = l.has_tcodes ? reinterpret_cast<uint4*>(base + l.tcodes) : nullptr;
+  h.n = n;
   h.n_pad = l.n_pad;
   h.m_stride = l.m_stride;
   return h;
+}
+
+__host__ __device__ inline HashImage hash_image(const HashBatch& hb, int im) {
+  return hash_image_at(hb.arena + 256ull * hb.img[im].off256, hb.img[im].n, hb.L, hb.m);
 }
 
 struct ProjConsts {
@@ -229,9 +236,9 @@ struct ProjConsts {
   const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
   unsigned long long* fixups;  // running counts: [0] fp64 recomputes, [1] bits they changed
-  uint32_t* fixlist;        // [0] overflow flag, [1..n_waves] per-wave counts, then
+  uint32_t* fixlist;        // [0] overflow word (the seq of the last batch that
+                            // overflowed), [1..n_waves] per-wave counts, then
                             // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d)
-  uint32_t* fixflips;       // kMaxProjWaves: bits each k_fixup wavefront changed
   uint32_t fix_cap;         // entries the list holds
   int32_t n_waves;          // projection wavefronts of the launch (set by launch_project)
   int32_t R;                // 128 + L*m
@@ -239,16 +246,19 @@ struct ProjConsts {
 
 static_assert(sizeof(HashBatch) + sizeof(ProjConsts) <= 2048, "hashing kernel arguments too large");
 
-// Fix-up list capacity and the per-batch descriptor budget that keeps the
-// expected list (about 1.6 entries per descriptor) well inside it.
+// Fix-up list capacity; a batch holds at most kHashBatchDescs descriptors,
+// fewer when fixup_rel makes the expected list (about 2800 fixup_rel
+// entries per descriptor) more than half the capacity.
 constexpr uint32_t kFixListCap = 1u << 22;
 constexpr int kMaxProjWaves = 8192;
-constexpr int kHashBatchDescs = 1 << 20;
+constexpr int kHashBatchDescs = 1 << 22;
 
 // Host-side launchers (defined in the .hip files).
 hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, int n_cu,
                           hipStream_t s);
-hipError_t launch_buckets(const HashBatch& hb, hipStream_t s);
+// Bucket tables of the batch, then the bucket-ordered code copies of its
+// images that have one (n_xcd: XCDs the work-groups are dealt to).
+hipError_t launch_buckets(const HashBatch& hb, int n_xcd, hipStream_t s);
 hipError_t launch_match(const MatchArgs& a, int K, int wg, bool lds, bool persistent, int grid,
                         hipStream_t s);
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int n, hipStream_t s);

@@ -23,8 +23,9 @@
 // the global fix-up list, without atomics.
 // k_fixup: wavefronts walk the regions; each lane recomputes one entry
 // exactly in fp64 and patches its bit with a 32-bit atomic.  If a region
-// overflowed (adversarial inputs only), k_fixup_all instead rebuilds every
-// code and bucket id of the batch from exact values.
+// overflowed (adversarial inputs only: the overflow word then holds the
+// batch's number), it instead rebuilds every code and bucket id of the
+// batch from exact values.
 #include "chm_internal.h"
 
 namespace chm {
@@ -112,7 +113,7 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
   for (int tile = blockIdx.x * kProjWaves + wave; tile < total_tiles;
        tile += gridDim.x * kProjWaves) {
     while (tile >= hb.tile_prefix[im + 1]) ++im;
-    const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
+    const HashImage I = hash_image(hb, im);
     const int d0 = (tile - hb.tile_prefix[im]) * 32;
     const int dr = d0 + col;
     const bool valid = dr < I.n;
@@ -241,7 +242,7 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
   }
   if (lane == 0) {
     pc.fixlist[1 + gw] = wcount;
-    if (wcount > cap_w) atomicOr(pc.fixlist, 1u);
+    if (wcount > cap_w) atomicExch(pc.fixlist, hb.seq);
   }
 }
 
@@ -299,63 +300,87 @@ __device__ __forceinline__ double exact_projection_lds(const uint8_t* xr, const 
 
 constexpr int kFixWG = 512;
 
+// Without an overflow of the batch's fix-up list: wavefronts walk the
+// regions, each lane recomputes one listed projection exactly and patches
+// its bit.  After an overflow (adversarial inputs only) every work-group
+// instead rebuilds its share of the codes and bucket ids of the batch from
+// exact values.  Either way each work-group adds its counts (projections
+// recomputed, bits they changed) to the store's counters with one atomic
+// per counter.
 __global__ __launch_bounds__(kFixWG) void k_fixup(HashBatch hb, ProjConsts pc) {
   __shared__ uint16_t sW[kRowsPad * kWStride];
-  if (pc.fixlist[0] != 0) return;  // overflow: k_fixup_all rebuilds the batch
-  for (int c = threadIdx.x; c < kRowsPad * kDim / 8; c += kFixWG) {
-    const int r = c / (kDim / 8), k8 = c % (kDim / 8);
-    *reinterpret_cast<uint4*>(sW + r * kWStride + 8 * k8) = reinterpret_cast<const uint4*>(pc.W)[c];
-  }
-  __syncthreads();
-  const uint32_t cap_w = pc.fix_cap / pc.n_waves;
-  const uint32_t* counts = pc.fixlist + 1;
-  const uint32_t* entries = pc.fixlist + 1 + pc.n_waves;
-  const int lane = __lane_id();
-  // a wavefront takes whole regions; its lanes stride inside one
-  const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kFixWG / 64) + (threadIdx.x >> 6)));
-  const int nw = gridDim.x * (kFixWG / 64);
-  uint32_t flips = 0;
-  for (int r = wid; r < pc.n_waves; r += nw) {
-    const uint32_t count = counts[r];
-    for (uint32_t k = lane; k < count; k += 64) {
-      const uint32_t ent = entries[(size_t)r * cap_w + k];
-      const int im = ent >> 24, row = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
-      const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
-      const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kWStride, pc.cmu[row]);
-      bool changed;
-      if (row < 128) {
-        changed = set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
-      } else {
-        const int t = (row - 128) / hb.m, j = (row - 128) % hb.m;
-        const size_t byte = (size_t)t * I.n_pad + d;
-        uint32_t* w = reinterpret_cast<uint32_t*>(I.ids + (byte & ~(size_t)3));
-        changed = set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
-      }
-      flips += __popcll(__ballot(changed));
-    }
-  }
-  // per-wavefront slot, summed by k_fixup_all (no contended atomics)
-  if (lane == 0) pc.fixflips[wid] = flips;
-}
-
-// Adds the batch's fix-up count (the region counts) and changed bits (the
-// k_fixup slots) to the store's running counters: the entries are spread
-// over the whole grid, each work-group sums its share in LDS and adds it
-// with one atomic per counter.
-__device__ void fix_count(const ProjConsts& pc, int n_fix_waves) {
   __shared__ unsigned long long s_sum[2];
   if (threadIdx.x < 2) s_sum[threadIdx.x] = 0;
-  __syncthreads();
-  unsigned long long a = 0, b = 0;
-  const int n = pc.n_waves + n_fix_waves;
-  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
-    if (i < pc.n_waves)
-      a += pc.fixlist[1 + i];
-    else
-      b += pc.fixflips[i - pc.n_waves];
+  unsigned long long n_fix = 0, n_flip = 0;
+  const int lane = __lane_id();
+  if (pc.fixlist[0] == hb.seq) {
+    const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
+    const int gsize = gridDim.x * blockDim.x;
+    const int total = hb.tile_prefix[hb.count] * 32;
+    for (int g = gtid; g < total; g += gsize) {
+      int im = 0;
+      while (g >= hb.tile_prefix[im + 1] * 32) ++im;
+      const HashImage I = hash_image(hb, im);
+      const int d = g - hb.tile_prefix[im] * 32;
+      if (d >= I.n) continue;
+      uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
+#pragma unroll 1
+      for (int r = 0; r < pc.R; ++r) {
+        const double p = exact_projection(I.desc + (size_t)d * kDim, pc.W + r * kDim, pc.cmu[r]);
+        const uint32_t bit = p > 0.0 ? 1u << (r & 31) : 0u;
+        const int slot = r < 128 ? (r >> 5) : 4 + ((r - 128) >> 5);
+        w0 |= slot == 0 ? bit : 0u; w1 |= slot == 1 ? bit : 0u; w2 |= slot == 2 ? bit : 0u;
+        w3 |= slot == 3 ? bit : 0u; w4 |= slot == 4 ? bit : 0u; w5 |= slot == 5 ? bit : 0u;
+      }
+      const uint4 old = I.codes[d];
+      uint32_t flips = __popc(old.x ^ w0) + __popc(old.y ^ w1) + __popc(old.z ^ w2) + __popc(old.w ^ w3);
+      I.codes[d] = make_uint4(w0, w1, w2, w3);
+      const uint64_t bb = (uint64_t)w4 | ((uint64_t)w5 << 32);
+      const uint32_t mask = (1u << hb.m) - 1u;
+      for (int t = 0; t < hb.L; ++t) {
+        const uint8_t nb = (uint8_t)((uint32_t)(bb >> (hb.m * t)) & mask);
+        flips += __popc((uint32_t)(I.ids[(size_t)t * I.n_pad + d] ^ nb));
+        I.ids[(size_t)t * I.n_pad + d] = nb;
+      }
+      n_fix += (unsigned long long)pc.R;
+      n_flip += flips;
+    }
+  } else {
+    for (int c = threadIdx.x; c < kRowsPad * kDim / 8; c += kFixWG) {
+      const int r = c / (kDim / 8), k8 = c % (kDim / 8);
+      *reinterpret_cast<uint4*>(sW + r * kWStride + 8 * k8) = reinterpret_cast<const uint4*>(pc.W)[c];
+    }
+    __syncthreads();
+    const uint32_t cap_w = pc.fix_cap / pc.n_waves;
+    const uint32_t* counts = pc.fixlist + 1;
+    const uint32_t* entries = pc.fixlist + 1 + pc.n_waves;
+    // a wavefront takes whole regions; its lanes stride inside one
+    const int wid = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (kFixWG / 64) + (threadIdx.x >> 6)));
+    const int nw = gridDim.x * (kFixWG / 64);
+    for (int r = wid; r < pc.n_waves; r += nw) {
+      const uint32_t count = counts[r];
+      if (lane == 0) n_fix += count;
+      for (uint32_t k = lane; k < count; k += 64) {
+        const uint32_t ent = entries[(size_t)r * cap_w + k];
+        const int im = ent >> 24, row = (ent >> 16) & 0xFF, d = ent & 0xFFFF;
+        const HashImage I = hash_image(hb, im);
+        const double p = exact_projection_lds(I.desc + (size_t)d * kDim, sW + row * kWStride, pc.cmu[row]);
+        bool changed;
+        if (row < 128) {
+          changed = set_bit(reinterpret_cast<uint32_t*>(I.codes + d) + (row >> 5), 1u << (row & 31), p > 0.0);
+        } else {
+          const int t = (row - 128) / hb.m, j = (row - 128) % hb.m;
+          const size_t byte = (size_t)t * I.n_pad + d;
+          uint32_t* w = reinterpret_cast<uint32_t*>(I.ids + (byte & ~(size_t)3));
+          changed = set_bit(w, 1u << (8 * (byte & 3) + j), p > 0.0);
+        }
+        if (changed) ++n_flip;
+      }
+    }
   }
-  if (a) atomicAdd(&s_sum[0], a);
-  if (b) atomicAdd(&s_sum[1], b);
+  __syncthreads();  // s_sum is cleared
+  if (n_fix) atomicAdd(&s_sum[0], n_fix);
+  if (n_flip) atomicAdd(&s_sum[1], n_flip);
   __syncthreads();
   if (threadIdx.x == 0) {
     if (s_sum[0]) atomicAdd(pc.fixups, s_sum[0]);
@@ -363,53 +388,10 @@ __device__ void fix_count(const ProjConsts& pc, int n_fix_waves) {
   }
 }
 
-// Without an overflow of the fix-up list, the work-groups only count.
-// After one, every work-group rebuilds its share of the codes and bucket ids
-// of the batch from exact values (adversarial inputs only).
-__global__ __launch_bounds__(256) void k_fixup_all(HashBatch hb, ProjConsts pc, int n_fix_waves) {
-  if (pc.fixlist[0] == 0) {
-    fix_count(pc, n_fix_waves);
-    return;
-  }
-  const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
-  const int gsize = gridDim.x * blockDim.x;
-  const int total = hb.tile_prefix[hb.count] * 32;
-  for (int g = gtid; g < total; g += gsize) {
-    int im = 0;
-    while (g >= hb.tile_prefix[im + 1] * 32) ++im;
-    const HashImage I = hash_image(hb.img[im], hb.L, hb.m);
-    const int d = g - hb.tile_prefix[im] * 32;
-    if (d >= I.n) continue;
-    uint32_t w0 = 0, w1 = 0, w2 = 0, w3 = 0, w4 = 0, w5 = 0;
-#pragma unroll 1
-    for (int r = 0; r < pc.R; ++r) {
-      const double p = exact_projection(I.desc + (size_t)d * kDim, pc.W + r * kDim, pc.cmu[r]);
-      const uint32_t bit = p > 0.0 ? 1u << (r & 31) : 0u;
-      const int slot = r < 128 ? (r >> 5) : 4 + ((r - 128) >> 5);
-      w0 |= slot == 0 ? bit : 0u; w1 |= slot == 1 ? bit : 0u; w2 |= slot == 2 ? bit : 0u;
-      w3 |= slot == 3 ? bit : 0u; w4 |= slot == 4 ? bit : 0u; w5 |= slot == 5 ? bit : 0u;
-    }
-    const uint4 old = I.codes[d];
-    uint32_t flips = __popc(old.x ^ w0) + __popc(old.y ^ w1) + __popc(old.z ^ w2) + __popc(old.w ^ w3);
-    I.codes[d] = make_uint4(w0, w1, w2, w3);
-    const uint64_t bb = (uint64_t)w4 | ((uint64_t)w5 << 32);
-    const uint32_t mask = (1u << hb.m) - 1u;
-    for (int t = 0; t < hb.L; ++t) {
-      const uint8_t nb = (uint8_t)((uint32_t)(bb >> (hb.m * t)) & mask);
-      flips += __popc((uint32_t)(I.ids[(size_t)t * I.n_pad + d] ^ nb));
-      I.ids[(size_t)t * I.n_pad + d] = nb;
-    }
-    if (flips) atomicAdd(pc.fixups + 1, (unsigned long long)flips);
-  }
-  if (gtid == 0) atomicAdd(pc.fixups, (unsigned long long)total * pc.R);
-}
-
 hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, int n_cu,
                           hipStream_t s) {
   const int tiles = hb.tile_prefix[hb.count];
   if (tiles == 0) return hipSuccess;
-  hipError_t e = launch_fill_u32(pc.fixlist, 0u, 1, s);
-  if (e != hipSuccess) return e;
   int grid = (tiles + kProjWaves - 1) / kProjWaves;
   if (grid > CHM_PROJ_GRID_PER_CU * n_cu) grid = CHM_PROJ_GRID_PER_CU * n_cu;
   if (grid * kProjWaves > kMaxProjWaves) grid = kMaxProjWaves / kProjWaves;
@@ -419,12 +401,9 @@ hipError_t launch_project(const HashBatch& hb, const ProjConsts& pc, int fp32, i
     hipLaunchKernelGGL(k_project<true>, dim3(grid), dim3(kProjWG), 0, s, hb, p2);
   else
     hipLaunchKernelGGL(k_project<false>, dim3(grid), dim3(kProjWG), 0, s, hb, p2);
-  e = hipGetLastError();
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  int fgrid = 2 * n_cu;
-  if (fgrid * (kFixWG / 64) > kMaxProjWaves) fgrid = kMaxProjWaves / (kFixWG / 64);
-  hipLaunchKernelGGL(k_fixup, dim3(fgrid), dim3(kFixWG), 0, s, hb, p2);
-  hipLaunchKernelGGL(k_fixup_all, dim3(4 * n_cu), dim3(256), 0, s, hb, p2, fgrid * (kFixWG / 64));
+  hipLaunchKernelGGL(k_fixup, dim3(2 * n_cu), dim3(kFixWG), 0, s, hb, p2);
   return hipGetLastError();
 }
 
