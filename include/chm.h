@@ -96,6 +96,13 @@ const char *chm_last_error(void);
 /* ABI version of the loaded library (CHM_ABI_VERSION it was built with). */
 int32_t chm_abi_version(void);
 
+/* Test hook for the CHM_E_HIP error path: the n-th HIP runtime call the
+ * library checks on the calling thread after this call (n >= 1) is not
+ * made and reports a failure, so the entry point making it returns
+ * CHM_E_HIP (its outputs are then unspecified, as for any error); n = 0
+ * cancels a pending failure.  Later calls run normally. */
+void chm_debug_fail_hip(int32_t n);
+
 /* ------------------------------------------------------------------ store
  * A store keeps images resident in a caller-owned device arena: the raw
  * descriptors and everything step (1)-(2) of Sec. 2.3.1 builds for them
@@ -317,6 +324,21 @@ typedef struct chm_schedule chm_schedule;
 chm_status chm_schedule_mbr(int32_t n_images, const int32_t *pairs, int32_t n_pairs,
                             const uint64_t *image_bytes, uint64_t cap_bytes, int32_t blk_images,
                             chm_schedule **out);
+/* A schedule given step by step, for running other data schedules (the
+ * per-pair, load/free-list and graph-partition schedules Sec. 2.2 compares
+ * MBR with, Fig. 2b) through chm_run_schedule.  Step k frees
+ * evict_ids[evict_offs[k] .. evict_offs[k+1]), loads load_ids[load_offs[k]
+ * ..] and matches the pairs (indices into `pairs`) pair_ids[pair_offs[k]
+ * ..]; each offsets array has n_steps + 1 entries starting at 0.  The call
+ * replays the residency and rejects (CHM_E_INVALID_ARG, naming the step) an
+ * eviction of an absent image, a load of a resident one, resident bytes
+ * above cap_bytes after a step's loads, a pair listed twice or in no step,
+ * or a pair whose images are not resident at its step. */
+chm_status chm_schedule_from_steps(int32_t n_images, int32_t n_pairs, const int32_t *pairs,
+                                   const uint64_t *image_bytes, uint64_t cap_bytes, int32_t n_steps,
+                                   const int32_t *evict_offs, const int32_t *evict_ids,
+                                   const int32_t *load_offs, const int32_t *load_ids,
+                                   const int32_t *pair_offs, const int32_t *pair_ids, chm_schedule **out);
 int32_t chm_schedule_num_steps(const chm_schedule *s);
 /* Pointers stay valid until chm_schedule_free. */
 chm_status chm_schedule_step(const chm_schedule *s, int32_t step, const int32_t **evict,

@@ -62,12 +62,12 @@ KERNEL_BUCKET_MAJOR = 1
 
 # every symbol include/chm.h declares
 EXPORTS = [
-    "chm_config_default", "chm_last_error", "chm_abi_version", "chm_image_bytes",
+    "chm_config_default", "chm_last_error", "chm_abi_version", "chm_debug_fail_hip", "chm_image_bytes",
     "chm_store_overhead_bytes", "chm_store_create", "chm_store_destroy", "chm_store_load",
     "chm_store_rehash", "chm_store_evict", "chm_store_image_feats", "chm_store_stats",
     "chm_debug_image", "chm_plan_create", "chm_plan_execute", "chm_plan_destroy",
     "chm_match_pairs", "chm_store_get_tuning", "chm_store_set_tuning",
-    "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_bruteforce_noalloc", "chm_schedule_mbr", "chm_schedule_num_steps",
+    "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_bruteforce_noalloc", "chm_schedule_mbr", "chm_schedule_from_steps", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
     "chm_run_schedule_sao", "chm_ransac_filter",
@@ -88,6 +88,7 @@ def lib():
             "chm_config_default": (None, [P(Config)]),
             "chm_last_error": (C.c_char_p, []),
             "chm_abi_version": (i32, []),
+            "chm_debug_fail_hip": (None, [i32]),
             "chm_image_bytes": (i32, [P(Config), i32, P(u64)]),
             "chm_store_overhead_bytes": (i32, [P(Config), P(u64)]),
             "chm_store_create": (i32, [P(Config), vp, vp, vp, u64, P(vp)]),
@@ -108,6 +109,7 @@ def lib():
             "chm_bruteforce": (i32, [vp, i32, vp, i32, i32, i32, vp, vp, u64, vp]),
             "chm_bruteforce_noalloc": (i32, [vp, i32, vp, i32, i32, i32, vp, vp]),
             "chm_schedule_mbr": (i32, [i32, vp, i32, vp, u64, i32, P(vp)]),
+            "chm_schedule_from_steps": (i32, [i32, i32, vp, vp, u64, i32, vp, vp, vp, vp, vp, vp, P(vp)]),
             "chm_schedule_num_steps": (i32, [vp]),
             "chm_schedule_step": (i32, [vp, i32, P(P(i32)), P(i32), P(P(i32)), P(i32), P(P(i32)), P(i32)]),
             "chm_schedule_info": (i32, [vp, P(i32), P(i32), P(P(i32)), P(P(i32))]),
@@ -340,6 +342,11 @@ def match_pairs(store: Store, pairs, out, mode=MATCH_BATCHED, stream=None, offs=
     return offs
 
 
+def debug_fail_hip(n: int) -> None:
+    """Test hook: the n-th checked HIP call of this thread fails (0 cancels)."""
+    lib().chm_debug_fail_hip(int(n))
+
+
 def bruteforce_work_bytes(nq: int, nd: int) -> int:
     out = C.c_uint64()
     _check(lib().chm_bruteforce_work_bytes(int(nq), int(nd), C.byref(out)))
@@ -397,6 +404,30 @@ def schedule_mbr(n_images: int, pairs: np.ndarray, image_bytes_: Sequence[int], 
     else:
         L.chm_schedule_free(h)
     return sch
+
+
+def schedule_from_steps(n_images: int, pairs: np.ndarray, image_bytes_: Sequence[int], cap_bytes: int,
+                        steps: Sequence[dict]) -> Schedule:
+    """A library schedule (with its handle, for run_schedule) from explicit
+    steps, each a dict of evict / load / pairs lists (chm_schedule_from_steps
+    checks the residency they imply)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    sizes = np.ascontiguousarray(image_bytes_, dtype=np.uint64)
+
+    def csr(key):
+        offs = np.zeros(len(steps) + 1, np.int32)
+        offs[1:] = np.cumsum([len(s[key]) for s in steps])
+        ids = np.ascontiguousarray(np.concatenate([np.asarray(s[key], np.int32) for s in steps])
+                                   if steps else np.zeros(0, np.int32), dtype=np.int32)
+        return offs, ids
+
+    (eo, ei), (lo, li), (po, pi) = csr("evict"), csr("load"), csr("pairs")
+    h = C.c_void_p()
+    _check(lib().chm_schedule_from_steps(int(n_images), len(pairs), _np_ptr(pairs), _np_ptr(sizes),
+                                         int(cap_bytes), len(steps), _np_ptr(eo), _np_ptr(ei), _np_ptr(lo),
+                                         _np_ptr(li), _np_ptr(po), _np_ptr(pi), C.byref(h)))
+    return Schedule(steps=[dict(evict=list(s["evict"]), load=list(s["load"]), pairs=list(s["pairs"]))
+                           for s in steps], iterations=0, fallback_pairs=0, dims=[], bandwidths=[], handle=h)
 
 
 def schedule_free(s: Schedule) -> None:

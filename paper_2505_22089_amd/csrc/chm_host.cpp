@@ -33,9 +33,20 @@ chm_status chm::fail(chm_status st, const char* fmt, ...) {
 
 void chm::clear_error() { g_err.clear(); }
 
+// Test hook (chm_debug_fail_hip): checked HIP calls of this thread left
+// before the one that reports a failure without being made (0: none).
+static thread_local int g_hip_fault_in = 0;
+
+bool chm::hip_fault_due() {
+  if (g_hip_fault_in <= 0) return false;
+  return --g_hip_fault_in == 0;
+}
+
+extern "C" void chm_debug_fail_hip(int32_t n) { g_hip_fault_in = n > 0 ? n : 0; }
+
 #define HIPCHK(call)                                                                     \
   do {                                                                                   \
-    hipError_t e_ = (call);                                                              \
+    hipError_t e_ = chm::hip_fault_due() ? hipErrorUnknown : (call);                     \
     if (e_ != hipSuccess)                                                                \
       return chm::fail(CHM_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_));        \
   } while (0)
@@ -119,9 +130,9 @@ static const uint64_t kHdrCmu = kHdrTau + round_up(3 * kRowsPad * 4, 256);
 static const uint64_t kHdrMu = kHdrCmu + round_up(kRowsPad * 8, 256);
 static const uint64_t kHdrFix = kHdrMu + 256;
 static const uint64_t kHdrFixList = kHdrFix + 256;
-// fix-up list: overflow flag, per-wave counts, regions, then per-wave flips
+// fix-up list: overflow word, per-wave counts, regions
 static const uint64_t kHdrBytes =
-    kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + 2 * (uint64_t)kMaxProjWaves) * 4, 256);
+    kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + (uint64_t)kMaxProjWaves) * 4, 256);
 
 extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
   clear_error();
@@ -158,6 +169,7 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   if (!h_W || !h_mu || !d_arena || !out) return fail(CHM_E_INVALID_ARG, "NULL argument");
   if (((uintptr_t)d_arena) % 256) return fail(CHM_E_INVALID_ARG, "arena must be 256-byte aligned");
   if (arena_bytes < kHdrBytes) return fail(CHM_E_CAPACITY, "arena smaller than the store header");
+  if (arena_bytes > (256ull << 32)) return fail(CHM_E_INVALID_ARG, "arena larger than 1 TiB");
   const int R = CHM_CODE_BITS + cfg->num_tables * cfg->bucket_bits;
   for (int i = 0; i < R * kDim; ++i)
     if (!bf16_ok(h_W[i]))
@@ -236,6 +248,8 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   if (e == hipSuccess) e = hipMemcpy(S->dMu, h_mu, kDim, hipMemcpyHostToDevice);
   unsigned long long zero[2] = {0, 0};  // fix-ups, flips
   if (e == hipSuccess) e = hipMemcpy(S->dFix, zero, sizeof zero, hipMemcpyHostToDevice);
+  // the fix-up list's overflow word: no batch (batch numbers start at 1)
+  if (e == hipSuccess) e = hipMemcpy(S->dFixList, zero, 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete S;
@@ -253,11 +267,7 @@ extern "C" void chm_store_destroy(chm_store* S) {
 }
 
 HashImage chm::hash_image_of(const chm_store* S, const ImageSlot& sl) {
-  HashSlot hs;
-  hs.base = S->base + sl.off;
-  hs.n = sl.n;
-  hs.reserved = 0;
-  return hash_image(hs, S->cfg.num_tables, S->cfg.bucket_bits);
+  return hash_image_at(S->base + sl.off, sl.n, S->cfg.num_tables, S->cfg.bucket_bits);
 }
 
 chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& slots, hipStream_t s) {
@@ -269,18 +279,23 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
   pc.fixups = S->dFix;
   pc.fixlist = S->dFixList;
   pc.fix_cap = kFixListCap;
-  pc.fixflips = S->dFixList + 1 + kMaxProjWaves + kFixListCap;
   pc.R = S->R;
+  // descriptors per batch: the expected fix-up list (about 2800 fixup_rel
+  // entries per descriptor) at most half the list
+  const double per_desc = 2800.0 * S->cfg.fixup_rel;
+  const int budget = (int)std::max(65536.0, std::min((double)kHashBatchDescs, kFixListCap / (2.0 * per_desc)));
   for (size_t i0 = 0; i0 < slots.size();) {
     HashBatch hb;
     std::memset(&hb, 0, sizeof hb);
+    hb.arena = S->base;
     hb.L = S->cfg.num_tables;
     hb.m = S->cfg.bucket_bits;
+    hb.seq = ++S->hash_seq == 0 ? ++S->hash_seq : S->hash_seq;  // never 0 (the word's initial value)
     int cnt = 0, tiles = 0;
     int descs = 0;
     for (size_t i = i0; i < slots.size() && cnt < kHashBatch; ++i, ++cnt) {
-      if (cnt > 0 && descs + slots[i]->n > kHashBatchDescs) break;
-      hb.img[cnt].base = S->base + slots[i]->off;
+      if (cnt > 0 && descs + slots[i]->n > budget) break;
+      hb.img[cnt].off256 = (uint32_t)(slots[i]->off / 256);
       hb.img[cnt].n = slots[i]->n;
       hb.tile_prefix[cnt] = tiles;
       tiles += (slots[i]->n + 31) / 32;
@@ -290,7 +305,7 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
     for (int k = cnt + 1; k <= kHashBatch; ++k) hb.tile_prefix[k] = tiles;
     hb.count = cnt;
     HIPCHK(launch_project(hb, pc, S->cfg.proj_precision == CHM_PROJ_FP32, S->n_cu, s));
-    HIPCHK(launch_buckets(hb, s));
+    HIPCHK(launch_buckets(hb, S->n_xcd, s));
     i0 += cnt;
   }
   return CHM_OK;

@@ -15,6 +15,9 @@ namespace chm {
 
 chm_status fail(chm_status st, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
 void clear_error();
+// True when the test hook (chm_debug_fail_hip) says this checked HIP call
+// is to fail without being made.
+bool hip_fault_due();
 
 // First-fit sub-allocator over [0, size) of the caller's arena, 256-byte granules.
 struct Arena {
@@ -56,6 +59,7 @@ struct chm_store {
   int lds_top = 0;  // byte address of the match kernel's LDS control words
   int device = 0;
   hipStream_t cap_stream = nullptr;
+  uint32_t hash_seq = 0;  // number of the last hash batch (its fix-up overflow mark)
 };
 
 struct chm_plan {

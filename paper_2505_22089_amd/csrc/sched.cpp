@@ -402,6 +402,87 @@ extern "C" chm_status chm_schedule_mbr(int32_t n_images, const int32_t* pairs, i
   return CHM_OK;
 }
 
+extern "C" chm_status chm_schedule_from_steps(int32_t n_images, int32_t n_pairs, const int32_t* pairs,
+                                              const uint64_t* image_bytes, uint64_t cap_bytes, int32_t n_steps,
+                                              const int32_t* evict_offs, const int32_t* evict_ids,
+                                              const int32_t* load_offs, const int32_t* load_ids,
+                                              const int32_t* pair_offs, const int32_t* pair_ids,
+                                              chm_schedule** out) {
+  clear_error();
+  if (n_images < 0 || n_pairs < 0 || n_steps < 0) return fail(CHM_E_INVALID_ARG, "negative size");
+  if (!out || !evict_offs || !load_offs || !pair_offs || (n_pairs && !pairs) || (n_images && !image_bytes))
+    return fail(CHM_E_INVALID_ARG, "NULL argument");
+  if (evict_offs[0] != 0 || load_offs[0] != 0 || pair_offs[0] != 0)
+    return fail(CHM_E_INVALID_ARG, "step offsets must start at 0");
+  for (int k = 0; k < n_steps; ++k)
+    if (evict_offs[k + 1] < evict_offs[k] || load_offs[k + 1] < load_offs[k] || pair_offs[k + 1] < pair_offs[k])
+      return fail(CHM_E_INVALID_ARG, "step %d: decreasing offsets", k);
+  if ((evict_offs[n_steps] && !evict_ids) || (load_offs[n_steps] && !load_ids) || (pair_offs[n_steps] && !pair_ids))
+    return fail(CHM_E_INVALID_ARG, "NULL argument");
+  for (int p = 0; p < n_pairs; ++p)
+    if (pairs[2 * p] < 0 || pairs[2 * p] >= n_images || pairs[2 * p + 1] < 0 || pairs[2 * p + 1] >= n_images)
+      return fail(CHM_E_INVALID_ARG, "pair %d names an image outside 0..%d", p, n_images - 1);
+  // replay the residency: evictions of resident images, loads of absent
+  // ones, the cap after each step's loads, every pair once with both images
+  // resident
+  std::vector<char> res(n_images, 0), done(n_pairs, 0);
+  uint64_t used = 0;
+  chm_schedule* S = new chm_schedule();
+  for (int k = 0; k < n_steps; ++k) {
+    std::vector<int32_t> ev(evict_ids + evict_offs[k], evict_ids + evict_offs[k + 1]);
+    std::vector<int32_t> ld(load_ids + load_offs[k], load_ids + load_offs[k + 1]);
+    std::vector<int32_t> pp(pair_ids + pair_offs[k], pair_ids + pair_offs[k + 1]);
+    const char* err = nullptr;
+    int bad = -1;
+    for (int32_t i : ev) {
+      if (i < 0 || i >= n_images || !res[i]) {
+        err = "evicts an image that is not resident";
+        bad = i;
+        break;
+      }
+      res[i] = 0;
+      used -= image_bytes[i];
+    }
+    for (size_t x = 0; !err && x < ld.size(); ++x) {
+      const int32_t i = ld[x];
+      if (i < 0 || i >= n_images || res[i]) {
+        err = "loads an image that is resident or out of range";
+        bad = i;
+        break;
+      }
+      res[i] = 1;
+      used += image_bytes[i];
+    }
+    if (!err && used > cap_bytes) err = "exceeds the cap";
+    for (size_t x = 0; !err && x < pp.size(); ++x) {
+      const int32_t p = pp[x];
+      if (p < 0 || p >= n_pairs || done[p]) {
+        err = "lists a pair out of range or twice";
+        bad = p;
+      } else if (!res[pairs[2 * p]] || !res[pairs[2 * p + 1]]) {
+        err = "lists a pair whose images are not resident";
+        bad = p;
+      } else {
+        done[p] = 1;
+      }
+    }
+    if (err) {
+      delete S;
+      return fail(CHM_E_INVALID_ARG, "step %d %s (%d)", k, err, bad);
+    }
+    S->evict.push_back(std::move(ev));
+    S->load.push_back(std::move(ld));
+    S->pairs.push_back(std::move(pp));
+  }
+  for (int p = 0; p < n_pairs; ++p)
+    if (!done[p]) {
+      delete S;
+      return fail(CHM_E_INVALID_ARG, "pair %d is in no step", p);
+    }
+  *out = S;
+  return CHM_OK;
+}
+
 extern "C" int32_t chm_schedule_num_steps(const chm_schedule* s) {
   return s ? (int32_t)s->pairs.size() : 0;
 }
