@@ -52,6 +52,12 @@ def parse():
     ap.add_argument("--grid-shape", default="50,100,10000", help="grid workload: rows,cols,features")
     ap.add_argument("--grid-sao", action="store_true",
                     help="grid workload: also run the first cap with the device SAO filter per step")
+    ap.add_argument("--grid-study", default="",
+                    help="grid workload: caps in GB (e.g. 2,0.5) at which to run the schedule study on the "
+                         "device: MBR at every --study-blks Size_blk, the load/free-list and graph-partition "
+                         "schedules over all pairs, and the per-pair schedule over --naive-pairs pairs")
+    ap.add_argument("--study-blks", default="50,100,200,400,800")
+    ap.add_argument("--naive-pairs", type=int, default=2000)
     ap.add_argument("--precision", default="bf16", choices=["bf16", "fp32"])
     ap.add_argument("--no-reuse", action="store_true",
                     help="also time the plain path re-hashing both images of every pair "
@@ -159,9 +165,12 @@ def main():
         for pl in plans:
             pl.close()
     # batched path: launch shape chosen by the autotuner (results identical)
+    tune_report = None
     if args.tuning == "auto":
         from paper_2505_22089_amd import autotune
-        best = autotune.tune(store, wl.pairs, reps=3, cache=None)
+        tune_report = {}
+        store.set_tuning(**lib_tuning)
+        best = autotune.tune(store, wl.pairs, reps=3, cache=None, report=tune_report)
     else:
         store.set_tuning(**lib_tuning)
         if args.tuning != "default":
@@ -206,11 +215,24 @@ def main():
     K = wl.K
     alg_ops = 10 * cand + 32 * K * total_q
     achieved = alg_ops / (match_ms * 1e-3) / 1e12
+    tun = store.tuning_dict()
+    nd = np.array([wl.images[d].shape[0] for d in wl.pairs[:, 1]])
+    n_bm = int((nd >= tun["bm_min_db_feats"]).sum()) if tun["match_kernel"] == chm.KERNEL_BUCKET_MAJOR else 0
+    lds_cap = 10175
+    kernels = []
+    if n_bm < P:
+        kernels.append("k_match<%d,1024,%s,persistent> (query major, %d pairs)"
+                       % (8 if K > 4 else K, "LDS-staged codes" if (nd[nd < tun["bm_min_db_feats"]] <= lds_cap).any()
+                          else "HBM codes", P - n_bm))
+    if n_bm:
+        kernels.append("k_match_bm<%d> (bucket major, one launch per table and round, %d pairs)"
+                       % (8 if K > 4 else K, n_bm))
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(ALU_PEAK_TOPS, 2),
             "unit": "TOP/s", "frac": round(achieved / ALU_PEAK_TOPS, 4),
-            "traffic": recorded_traffic(),
-            "kernel": "k_match (batched, LDS-staged codes)",
-            "ops_per_launch": alg_ops}
+            "traffic": recorded_traffic(args.workload),
+            "kernel": " + ".join(kernels), "launch_us": round(match_ms * 1e3, 1),
+            "ops_per_launch": alg_ops,
+            "ops": "10 per candidate (4 xor, 4 popcount, key, compare) + 32 K per query (dot4 re-rank)"}
     # hashing stage against HBM, per descriptor: read 128 B, write the code
     # (16 B), L bucket ids (L B) and the norm (4 B); the table build reads the
     # L ids and writes L u16 members
@@ -239,8 +261,10 @@ def main():
                            "mfma_sign_errors_per_descriptor": flips_per_hash / n_desc},
         "roofline": roof,
     }
-    if args.workload != "knn-50x8000":
-        roof["traffic"] = None
+    if tune_report is not None:
+        res["autotune"] = {"default_tuning_match_ms": round(tune_report["default_ms"], 4),
+                           "tuned_match_ms": round(tune_report["best_ms"], 4),
+                           "tunings_timed": tune_report["timed"], "default_tuning": lib_tuning}
 
     if args.workload == "knn-200x40000":
         res["bruteforce"] = bruteforce_leg(wl, descs, stream)
@@ -291,6 +315,7 @@ def cpu_baseline(wl, gpu_out, min_seconds=10.0, max_reps=8):
         O.set_threads(threads)
     one = (t1 - t0) / len(need) * len(wl.images) + (t2 - t1) / len(sub) * P
     return {"value": round(P / t_step, 2), "unit": "pairs/s", "cores": threads, "kind": "oracle",
+            "cpu": cpu_model(),
             "sample": "the whole step (hash %d images + match all %d pairs) run %d times: %.1f s hashing, "
                       "%.1f s matching" % (len(wl.images), P, reps, t_hash, t_match),
             "gpu_identical_all_pairs": same,
@@ -450,14 +475,26 @@ def run_grid(args):
         store.close()
         del arena
         torch.cuda.empty_cache()
-    # sampled parity with the oracle
+    study = grid_study(args, wl, views, offs, sizes, cfg, out, say) if args.grid_study else None
+    # parity: every pair against the oracle's stored per-pair digests when
+    # they exist for this grid (tests/golden/make_digests.py), and a sample
+    # of pairs recomputed by the oracle
+    got = out.cpu().numpy()
+    name = "grid-%dx%d" % (rows * cols, nf)
+    digests = None
+    try:
+        from tests.digests import load_golden, pair_digests
+        dg, _, gp, _ = load_golden(name)
+        if np.array_equal(gp, wl.pairs):
+            digests = int((pair_digests(got, offs) == dg).sum())
+    except (OSError, KeyError):
+        pass
     from oracle import oracle as O
     rng = np.random.default_rng(9)
     idx = np.sort(rng.choice(P, 12, replace=False))
     need = sorted({int(i) for i in wl.pairs[idx].ravel()})
     H = O.hash_workload(wl, need)
     ref, so, _, _ = O.match_pairs(H, wl.pairs[idx], wl.L, wl.m, wl.K, wl.ratio)
-    got = out.cpu().numpy()
     same = all(np.array_equal(ref[so[k]:so[k + 1]], got[offs[p]:offs[p + 1]]) for k, p in enumerate(idx))
     binding = runs[-1]
     res = {"metric": METRIC, "value": binding["pairs_per_s"], "unit": "pairs/s", "n_gpus": 1, "steps": 1,
@@ -468,8 +505,82 @@ def run_grid(args):
                       "path": "MBR schedule: pinned host -> HBM per block row, hash + batched match"},
            "runs": runs, "h2d_floor_bytes": total,
            "naive_h2d_bytes": int(sum(feats[q] + feats[d] for q, d in wl.pairs) * 128),
-           "oracle_identical_on_sampled_pairs": bool(same), "sampled_pairs": int(len(idx))}
+           "oracle_identical_on_sampled_pairs": bool(same), "sampled_pairs": int(len(idx)),
+           "pairs_matching_oracle_digests": digests, "pairs": P}
+    if study is not None:
+        res["schedule_study"] = study
     print(json.dumps(res), flush=True)
+
+
+def grid_study(args, wl, views, offs, sizes, cfg, out, say):
+    """Data schedules of Sec. 2.2 run through the same device path (pinned
+    host memory -> HBM per step, hash, batched match, evict) at each study
+    cap: MBR at several Size_blk, the load/free list (pairs in list order,
+    least recently used images freed), the graph-partition part-pair
+    schedule and, on the first --naive-pairs pairs, the per-pair schedule
+    that loads both images of every pair.  Runs over all pairs are compared
+    with the oracle digests pair by pair when they are stored."""
+    import torch
+
+    from paper_2505_22089_amd import chm
+    from paper_2505_22089_amd import schedule_study as SS
+    n, P = len(wl.images), len(wl.pairs)
+    dev = out.device
+    desc = [int(x.shape[0]) * 128 for x in wl.images]
+    try:
+        from tests.digests import load_golden, pair_digests
+        dg, _, gp, _ = load_golden("grid-%dx%d" % (n, int(wl.images[0].shape[0])))
+        if not np.array_equal(gp, wl.pairs):
+            dg = None
+    except (OSError, KeyError):
+        dg = None
+    rows = []
+    for cap_gb in [float(c) for c in args.grid_study.split(",")]:
+        cap = int(cap_gb * (1 << 30))
+        runs = [("mbr", b) for b in [int(v) for v in args.study_blks.split(",")]]
+        runs += [("load/free list", None), ("graph partition", None), ("per pair", None)]
+        for kind, blk in runs:
+            sub = wl.pairs if kind != "per pair" else wl.pairs[:args.naive_pairs]
+            so = offs[:len(sub) + 1]
+            t0 = time.perf_counter()
+            if kind == "mbr":
+                sched = chm.schedule_mbr(n, sub, sizes, cap, blk, keep_handle=True)
+            elif kind == "load/free list":
+                sched = chm.schedule_from_steps(n, sub, sizes, cap, SS.lru_steps(sub, sizes, cap))
+            elif kind == "graph partition":
+                sched = chm.schedule_from_steps(n, sub, sizes, cap, SS.partition_steps(n, sub, sizes, cap))
+            else:
+                sched = chm.schedule_from_steps(n, sub, sizes, cap, SS.naive_steps(sub))
+            t_sched = time.perf_counter() - t0
+            arena = torch.empty(chm.store_overhead_bytes(cfg) + cap + (256 << 20), dtype=torch.uint8, device=dev)
+            store = chm.Store(cfg, wl.W, wl.mu, arena)
+            out.fill_(-7)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            chm.run_schedule(store, sched, sub, views, so, out)
+            torch.cuda.synchronize()
+            wall = time.perf_counter() - t0
+            st = store.stats()
+            row = {"cap_GB": cap_gb, "schedule": kind, "size_blk": blk, "pairs": int(len(sub)),
+                   "seconds": round(wall, 4), "pairs_per_s": round(len(sub) / wall, 1),
+                   "h2d_bytes": int(st.h2d_bytes), "h2d_over_floor": round(st.h2d_bytes / sum(desc), 3),
+                   "steps": len(sched.steps), "schedule_seconds": round(t_sched, 3),
+                   "resident_peak_bytes": int(st.resident_peak)}
+            if kind == "mbr":
+                row["mbr_dims"] = sched.dims
+                row["iterations"] = sched.iterations
+            if dg is not None:
+                got = out.cpu().numpy()
+                row["pairs_matching_oracle_digests"] = int((pair_digests(got[:int(so[-1])], so) ==
+                                                            dg[:len(sub)]).sum())
+            rows.append(row)
+            say("study cap %.2f GB %s%s: %.3f s, %.0f pairs/s, H2D %.2f GB"
+                % (cap_gb, kind, "" if blk is None else " blk %d" % blk, wall, len(sub) / wall, st.h2d_bytes / 1e9))
+            chm.schedule_free(sched)
+            store.close()
+            del arena
+            torch.cuda.empty_cache()
+    return rows
 
 
 def describe(wl):
@@ -513,11 +624,24 @@ def cpu_baseline_sampled(wl, gpu_out, offs, min_seconds=10.0):
     n_desc = sum(x.shape[0] for x in wl.images)
     t_full = t_hash * n_desc / max(1, n_hashed) + t_match * len(wl.pairs) / max(1, n_pairs)
     return {"value": round(len(wl.pairs) / t_full, 3), "unit": "pairs/s", "cores": O.max_threads(),
-            "kind": "oracle",
+            "kind": "oracle", "cpu": cpu_model(),
             "sample": "%d random pairs (%d images hashed, %.1f s; matching %.1f s), hashing scaled to "
                       "%d descriptors and matching to %d pairs" % (n_pairs, sum(h is not None for h in H),
                                                                    t_hash, t_match, n_desc, len(wl.pairs)),
             "gpu_identical_on_sample": same}
+
+
+def cpu_model():
+    """Host CPU model and the hardware threads the OS shows."""
+    name = "unknown"
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"model": name, "nproc": os.cpu_count()}
 
 
 def copy_calibration():
@@ -534,7 +658,8 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": n, "copies": 3}), flush=True)
 
 
-MATCH_SOURCES = ("bucket.hip", "chm_host.cpp", "chm_host.h", "chm_internal.h", "match.hip")
+MATCH_SOURCES = ("bucket.hip", "chm_host.cpp", "chm_host.h", "chm_internal.h", "match.hip", "match_bm.hip",
+                 "match_common.h")
 
 
 def sources_digest():
@@ -550,10 +675,10 @@ def sources_digest():
     return h.hexdigest()
 
 
-def recorded_traffic():
-    """HBM bytes per launch of the match kernel from the committed counter
+def recorded_traffic(workload):
+    """HBM bytes per match launch of a workload from the committed counter
     summary, or None when the native sources changed since it was taken."""
-    path = os.path.join(ROOT, "profiles", "k_match_knn-50x8000_traffic.txt")
+    path = os.path.join(ROOT, "profiles", "match_traffic_%s.txt" % workload)
     if not os.path.exists(path):
         return None
     rec = {}

@@ -1,37 +1,61 @@
 """Autotuner for the batched match launch.
 
-Chooses chm_tuning (queries per work item, work-group size, LDS staging of
-the db codes, persistent work-groups per compute unit) for a store and a
-pair list by timing the batched plan for each candidate on the device.  Any
-tuning gives identical results: every candidate's output is compared with
-the first one's and a mismatch raises.  Winners are cached in a JSON file
-keyed by the device name and the workload shape, so later runs skip the
-search.
+Chooses chm_tuning for a store and a pair list by timing the batched plan on
+the device: which match kernel serves which pairs (query major, bucket
+major, and the db-image size from which bucket major takes over), the
+bucket-major group size, and the query-major launch shape (queries per work
+item, work-group size, LDS staging of the db codes, persistent work-groups
+per compute unit, tail fraction, item size of launches without LDS staging).
+
+The search is coordinate descent from the library's defaults: each field in
+turn takes each of its candidate values with the others fixed, and the
+fastest value is kept before the next field is tried.  Any tuning gives
+identical results: every timed candidate's output is compared with the
+first one's and a mismatch raises.  Winners are cached in a JSON file keyed
+by the device name, a hash of the loaded library (a rebuilt kernel never
+reuses an old winner) and the workload shape, so later runs skip the search.
 """
 from __future__ import annotations
 
+import hashlib
 import json
 import os
 import time
-from typing import Dict, List, Optional
+from typing import Dict, List, Optional, Tuple
 
 import numpy as np
 
 from . import chm
 
-CANDIDATES: List[Dict[str, int]] = [
-    dict(queries_per_item=1024, wg_threads=1024, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=2048, wg_threads=1024, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=3072, wg_threads=1024, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=4096, wg_threads=1024, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=512, wg_threads=1024, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=1024, wg_threads=256, lds_codes=1, grid_per_cu=1),
-    dict(queries_per_item=1024, wg_threads=1024, lds_codes=0, grid_per_cu=2),
-    dict(queries_per_item=1024, wg_threads=256, lds_codes=0, grid_per_cu=2),
-    dict(queries_per_item=256, wg_threads=256, lds_codes=0, grid_per_cu=4),
+# candidate values per field, in the order the search visits the fields
+SEARCH: List[Tuple[str, List[int]]] = [
+    ("match_kernel", [chm.KERNEL_QUERY_MAJOR, chm.KERNEL_BUCKET_MAJOR]),
+    ("bm_min_db_feats", [0, 6144, 10176, 20000]),
+    ("group_queries", [32768, 65536, 98304, 196608]),
+    ("queries_per_item", [1024, 2048, 3072, 4096]),
+    ("wg_threads", [256, 1024]),
+    ("lds_codes", [0, 1]),
+    ("grid_per_cu", [1, 2, 4]),
+    ("tail_percent", [0, 4, 8, 16]),
+    ("hbm_item_queries", [256, 512, 1024]),
 ]
 
 DEFAULT_CACHE = os.path.join(os.path.expanduser("~"), ".cache", "chm_autotune.json")
+
+_LIB_HASH: Optional[str] = None
+
+
+def library_hash() -> str:
+    """sha256 (16 hex digits) of the loaded libchm.so."""
+    global _LIB_HASH
+    if _LIB_HASH is None:
+        chm.lib()
+        h = hashlib.sha256()
+        with open(chm.LIB_PATH, "rb") as f:
+            for block in iter(lambda: f.read(1 << 20), b""):
+                h.update(block)
+        _LIB_HASH = h.hexdigest()[:16]
+    return _LIB_HASH
 
 
 def _bucket(v: float) -> int:
@@ -44,9 +68,10 @@ def shape_key(store: "chm.Store", pairs: np.ndarray) -> str:
     nq = np.array([store.feats[int(q)] for q in pairs[:, 0]], dtype=np.float64)
     nd = np.array([store.feats[int(d)] for d in pairs[:, 1]], dtype=np.float64)
     c = store.cfg
-    return "%s|L%d m%d K%d|P%d|q%d|d%d|dmax%d" % (
-        dev, c.num_tables, c.bucket_bits, c.top_k, _bucket(len(pairs)), _bucket(nq.mean() if len(nq) else 1),
-        _bucket(nd.mean() if len(nd) else 1), _bucket(nd.max() if len(nd) else 1))
+    return "%s|lib %s|L%d m%d K%d|P%d|q%d|d%d|dmin%d|dmax%d" % (
+        dev, library_hash(), c.num_tables, c.bucket_bits, c.top_k, _bucket(len(pairs)),
+        _bucket(nq.mean() if len(nq) else 1), _bucket(nd.mean() if len(nd) else 1),
+        _bucket(nd.min() if len(nd) else 1), _bucket(nd.max() if len(nd) else 1))
 
 
 def _time_plan(store, pairs, offs, out, reps: int) -> float:
@@ -65,8 +90,12 @@ def _time_plan(store, pairs, offs, out, reps: int) -> float:
 
 
 def tune(store: "chm.Store", pairs: np.ndarray, reps: int = 5, cache: Optional[str] = DEFAULT_CACHE,
-         candidates: Optional[List[Dict[str, int]]] = None, verbose: bool = False) -> Dict[str, int]:
-    """Picks and applies the fastest tuning for this store and pair list."""
+         search: Optional[List[Tuple[str, List[int]]]] = None, verbose: bool = False,
+         report: Optional[dict] = None) -> Dict[str, int]:
+    """Picks and applies the fastest tuning for this store and pair list;
+    returns it (every chm_tuning field).  report, if given, receives the
+    default's and the winner's plan times (ms), the number of tunings timed
+    and whether the cache answered."""
     import torch
     pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
     key = shape_key(store, pairs)
@@ -79,29 +108,48 @@ def tune(store: "chm.Store", pairs: np.ndarray, reps: int = 5, cache: Optional[s
     if key in table:
         best = table[key]["tuning"]
         store.set_tuning(**best)
-        return best
+        if report is not None:
+            report.update(cached=True, best_ms=table[key]["ms"], default_ms=table[key].get("default_ms"),
+                          timed=0)
+        return store.tuning_dict()
     offs = chm.out_offsets(store, pairs)
     total = max(1, int(offs[-1]))
+    out = torch.empty(total, dtype=torch.int32, device=store.arena.device)
     ref = None
-    results = []
-    for cand in (candidates or CANDIDATES):
-        store.set_tuning(**cand)
-        out = torch.empty(total, dtype=torch.int32, device=store.arena.device)
-        t = _time_plan(store, pairs, offs, out, reps)
+    tried: Dict[str, float] = {}
+
+    def run(t: Dict[str, int]) -> float:
+        nonlocal ref
+        k = json.dumps(t, sort_keys=True)
+        if k in tried:
+            return tried[k]
+        store.set_tuning(**t)
+        out.fill_(-7)
+        ms = _time_plan(store, pairs, offs, out, reps) * 1e3
         o = out.cpu().numpy()
         if ref is None:
             ref = o
         elif not np.array_equal(o, ref):
-            raise RuntimeError("tuning %s changed the matches" % cand)
-        results.append((t, cand))
+            raise RuntimeError("tuning %s changed the matches" % t)
+        tried[k] = ms
         if verbose:
-            print("autotune %s: %.3f ms" % (cand, t * 1e3), flush=True)
-    results.sort(key=lambda x: x[0])
-    best = results[0][1]
+            print("autotune %s: %.3f ms" % (t, ms), flush=True)
+        return ms
+
+    best = store.tuning_dict()
+    best_ms = default_ms = run(best)
+    for field, values in (search or SEARCH):
+        for v in values:
+            cand = dict(best, **{field: int(v)})
+            ms = run(cand)
+            if ms < best_ms:
+                best, best_ms = cand, ms
     store.set_tuning(**best)
+    if report is not None:
+        report.update(cached=False, best_ms=best_ms, default_ms=default_ms, timed=len(tried))
     if cache:
-        table[key] = {"tuning": best, "ms": results[0][0] * 1e3,
-                      "tried": [{"tuning": c, "ms": t * 1e3} for t, c in results]}
+        table[key] = {"tuning": best, "ms": best_ms, "default_ms": default_ms,
+                      "tried": [{"tuning": json.loads(k), "ms": v} for k, v in sorted(tried.items(), key=lambda x: x[1])]}
         try:
             os.makedirs(os.path.dirname(cache), exist_ok=True)
             tmp = cache + ".tmp"
@@ -109,4 +157,4 @@ def tune(store: "chm.Store", pairs: np.ndarray, reps: int = 5, cache: Optional[s
             os.replace(tmp, cache)
         except OSError:
             pass
-    return best
+    return store.tuning_dict()

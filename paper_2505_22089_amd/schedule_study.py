@@ -108,6 +108,94 @@ def mbr(n: int, pairs: np.ndarray, slot_bytes: Sequence[int], desc_bytes: Sequen
             "dims": s.dims}
 
 
+# ---------------------------------------------------------------- step lists
+# The same schedules as explicit steps (evict, load, pairs) that the
+# library runs on the device (chm.schedule_from_steps + chm.run_schedule).
+
+def naive_steps(pairs: np.ndarray) -> List[dict]:
+    """One step per pair: its images loaded for it and freed after it (the
+    sequential per-pair strategy, with re-upload)."""
+    steps, res = [], []
+    for p, (q, d) in enumerate(np.asarray(pairs).reshape(-1, 2)):
+        need = sorted({int(q), int(d)})
+        steps.append({"evict": res, "load": need, "pairs": [p]})
+        res = need
+    return steps
+
+
+def lru_steps(pairs: np.ndarray, slot_bytes: Sequence[int], cap: int) -> List[dict]:
+    """Pairs in list order with a load/free list: a pair whose images are
+    resident (or fit beside the resident set) joins the current step; one
+    that needs room closes it, and the next step first frees the least
+    recently used images (never the pair's own) until its images fit."""
+    res: "OrderedDict[int, None]" = OrderedDict()
+    used = 0
+    steps: List[dict] = []
+    cur = {"evict": [], "load": [], "pairs": []}
+    for p, (q, d) in enumerate(np.asarray(pairs).reshape(-1, 2)):
+        q, d = int(q), int(d)
+        need = [i for i in dict.fromkeys((q, d)) if i not in res]
+        if used + sum(slot_bytes[i] for i in need) > cap:
+            if cur["pairs"]:
+                steps.append(cur)
+            cur = {"evict": [], "load": [], "pairs": []}
+            while used + sum(slot_bytes[i] for i in need) > cap:
+                victim = next(v for v in res if v not in (q, d))
+                used -= slot_bytes[victim]
+                del res[victim]
+                cur["evict"].append(victim)
+        for i in need:
+            res[i] = None
+            used += slot_bytes[i]
+            cur["load"].append(i)
+        for i in (q, d):
+            res.move_to_end(i)
+        cur["pairs"].append(p)
+    if cur["pairs"]:
+        steps.append(cur)
+    return steps
+
+
+def partition_steps(n: int, pairs: np.ndarray, slot_bytes: Sequence[int], cap: int) -> List[dict]:
+    """The part-pair schedule of graph_partition() as steps: part A is
+    loaded with its internal pairs, then each partner part B in turn (the
+    previous B freed first); A is freed before the next part A."""
+    edges = np.unique(np.sort(np.asarray(pairs, dtype=np.int32).reshape(-1, 2), axis=1), axis=0)
+    order = chm.gps_order(n, edges, list(range(n)))
+    part_of = np.empty(n, np.int64)
+    parts: List[List[int]] = [[]]
+    used = 0
+    for v in order:
+        if parts[-1] and used + slot_bytes[v] > cap // 2:
+            parts.append([])
+            used = 0
+        parts[-1].append(int(v))
+        part_of[v] = len(parts) - 1
+        used += slot_bytes[v]
+    by_parts: Dict[tuple, List[int]] = {}
+    for p, (q, d) in enumerate(np.asarray(pairs).reshape(-1, 2)):
+        a, b = sorted((int(part_of[q]), int(part_of[d])))
+        by_parts.setdefault((a, b), []).append(p)
+    steps: List[dict] = []
+    resident: List[int] = []
+    for a in range(len(parts)):
+        partners = sorted(b for (x, b) in by_parts if x == a and b != a)
+        if (a, a) not in by_parts and not partners:
+            continue
+        steps.append({"evict": resident, "load": list(parts[a]), "pairs": by_parts.get((a, a), [])})
+        resident = list(parts[a])
+        prev: List[int] = []
+        for b in partners:
+            steps.append({"evict": prev, "load": list(parts[b]), "pairs": by_parts[(a, b)]})
+            prev = list(parts[b])
+        resident = resident + prev
+    return steps
+
+
+def steps_h2d(steps: Sequence[dict], desc_bytes: Sequence[int]) -> int:
+    return int(sum(desc_bytes[i] for s in steps for i in s["load"]))
+
+
 def grid_graph(rows: int = 50, cols: int = 100, seed: int = 1005) -> np.ndarray:
     rng = np.random.default_rng(seed)
     return np.concatenate([synth.band_grid_pairs(rows, cols, 1, 3), synth.cross_links(rng, rows, cols)])

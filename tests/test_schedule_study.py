@@ -74,3 +74,52 @@ def test_graph_partition_covers_every_pair_once_within_the_cap():
     # everything fits in one part: each image is loaded once
     r = S.graph_partition(n, pairs, slot, desc, 2 * n * 10)
     assert r["parts"] == 1 and r["h2d_bytes"] == n * 8
+
+
+def _grid(rows=6, cols=12):
+    rng = np.random.default_rng(0)
+    return np.concatenate([synth.band_grid_pairs(rows, cols, 1, 3), synth.cross_links(rng, rows, cols)])
+
+
+def test_step_lists_are_valid_library_schedules_with_the_counted_traffic():
+    """The step lists of the per-pair, load/free-list and graph-partition
+    schedules pass the library's residency replay (every pair once, images
+    resident, cap kept) and copy exactly the bytes the counters report."""
+    from paper_2505_22089_amd import chm
+    pairs = _grid()
+    n = 72
+    rng = np.random.default_rng(3)
+    slot = [int(v) for v in rng.integers(8, 14, n)]
+    desc = [s * 7 for s in slot]
+    for cap in (60, 150, 10 ** 6):
+        lru = S.lru_steps(pairs, slot, cap)
+        assert S.steps_h2d(lru, desc) == S.sequential_lru(pairs, slot, desc, cap)["h2d_bytes"]
+        part = S.partition_steps(n, pairs, slot, cap)
+        assert S.steps_h2d(part, desc) == S.graph_partition(n, pairs, slot, desc, cap)["h2d_bytes"]
+        for steps in (lru, part, S.naive_steps(pairs)):
+            sch = chm.schedule_from_steps(n, pairs, slot, cap, steps)
+            chm.schedule_free(sch)
+    assert S.steps_h2d(S.naive_steps(pairs), desc) == S.naive_bytes(pairs, desc)
+
+
+def test_schedule_from_steps_rejects_broken_residency():
+    from paper_2505_22089_amd import chm
+    pairs = np.array([[0, 1], [1, 2]], np.int32)
+    slot = [10, 10, 10]
+    ok = [{"evict": [], "load": [0, 1], "pairs": [0]}, {"evict": [0], "load": [2], "pairs": [1]}]
+    chm.schedule_free(chm.schedule_from_steps(3, pairs, slot, 20, ok))
+    bad = [
+        [{"evict": [], "load": [0, 1, 2], "pairs": [0, 1]}],                                  # above the cap
+        [{"evict": [], "load": [0, 1], "pairs": [0, 1]}],                                     # image 2 absent
+        [{"evict": [], "load": [0, 1], "pairs": [0]}, {"evict": [2], "load": [], "pairs": [1]}],  # evicts absent
+        [{"evict": [], "load": [0, 1], "pairs": [0]}, {"evict": [], "load": [1], "pairs": [1]}],  # reloads 1
+        [{"evict": [], "load": [0, 1], "pairs": [0, 0]}],                                     # pair twice
+        [{"evict": [], "load": [0, 1], "pairs": [0]}],                                        # pair 1 missing
+    ]
+    for steps in bad:
+        try:
+            chm.schedule_from_steps(3, pairs, slot, 20, steps)
+        except chm.ChmError as e:
+            assert e.status == -1
+        else:
+            raise AssertionError("accepted %s" % steps)
