@@ -52,6 +52,9 @@ def parse():
     ap.add_argument("--grid-shape", default="50,100,10000", help="grid workload: rows,cols,features")
     ap.add_argument("--grid-sao", action="store_true",
                     help="grid workload: also run the first cap with the device SAO filter per step")
+    ap.add_argument("--grid-verify", action="store_true",
+                    help="grid workload: also run the first cap with the device SAO per step and RANSAC of "
+                         "every step on host threads beside the device (outlier removal included)")
     ap.add_argument("--grid-study", default="",
                     help="grid workload: caps in GB (e.g. 2,0.5) at which to run the schedule study on the "
                          "device: MBR at every --study-blks Size_blk, the load/free-list and graph-partition "
@@ -471,6 +474,30 @@ def run_grid(args):
                                            "input_errors": chm.sao_input_errors(work)}
             say("cap %.0f GB with SAO: %.3f s, %.0f pairs/s" % (cap_gb, wall_s, P / wall_s))
             del d_kps, work, filt
+        if args.grid_verify and cap_gb == float(args.caps.split(",")[0]):
+            # again, with RANSAC of every step on host threads beside the device
+            store.close()
+            store = chm.Store(cfg, wl.W, wl.mu, arena)
+            kps = synth.keypoints(wl)
+            d_kps = [torch.from_numpy(k).to(dev) for k in kps]
+            filt = torch.empty_like(out)
+            words = synth.ransac_words(P, 64)
+            h_filt = torch.empty(int(offs[-1]), dtype=torch.int32, pin_memory=True).numpy()
+            h_ver = np.empty(int(offs[-1]), np.int32)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            work = chm.run_schedule_verify(store, sched, wl.pairs, views, offs, out, d_kps, kps, filt, words,
+                                           h_filt, h_ver, iterations=64, thr=64, min_inliers=8)
+            torch.cuda.synchronize()
+            wall_v = time.perf_counter() - t0
+            runs[-1]["with_device_sao_host_ransac"] = {
+                "seconds": round(wall_v, 4), "pairs_per_s": round(P / wall_v, 1),
+                "matches": int((out.cpu().numpy() >= 0).sum()), "after_sao": int((h_filt >= 0).sum()),
+                "verified": int((h_ver >= 0).sum()), "host_threads": os.cpu_count(),
+                "ransac": "64 hypotheses, 4 px (64 units), at least 8 inliers",
+                "input_errors": chm.sao_input_errors(work)}
+            say("cap %.0f GB with SAO + RANSAC: %.3f s, %.0f pairs/s" % (cap_gb, wall_v, P / wall_v))
+            del d_kps, work, filt, h_filt, h_ver
         chm.schedule_free(sched)
         store.close()
         del arena

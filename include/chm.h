@@ -452,6 +452,32 @@ chm_status chm_run_schedule_sao(chm_store *store, const chm_schedule *s, const i
                                 int32_t score_den, int32_t *d_filtered, void *d_work,
                                 uint64_t work_bytes, void *stream);
 
+/* chm_run_schedule_sao with RANSAC of every block row on host threads,
+ * beside the device (Algorithm 1: outlier removal runs asynchronously with
+ * the matching of the next block rows): once a step's device work (its
+ * matching and SAO) ends, a worker thread copies the step's SAO output to
+ * h_filtered and runs chm_ransac_filter's verification of the step's pairs
+ * into h_verified, while the device goes on with the next steps.  The call
+ * returns when the device work and every step's RANSAC are done.
+ *   h_kp         : host array of n_images host keypoint arrays (the same
+ *                  points as d_kp), |x|, |y| < 2^19.
+ *   h_words, iterations, thr, min_inliers, n_threads : as in
+ *                  chm_ransac_filter, h_words indexed by the pair's position
+ *                  in h_pairs.
+ *   h_filtered   : host memory laid out like d_out (pinned memory makes the
+ *                  copies DMA transfers): receives the SAO output.
+ *   h_verified   : host memory laid out like d_out: the verified matches.
+ * Other arguments as in chm_run_schedule_sao.  A keypoint out of range, or a
+ * db row outside its image, fails the call with CHM_E_INVALID_ARG. */
+chm_status chm_run_schedule_verify(chm_store *store, const chm_schedule *s, const int32_t *h_pairs,
+                                   int32_t n_pairs, const void *const *h_descs, const int32_t *h_n_feats,
+                                   int32_t n_images, const int64_t *h_out_offsets, int32_t *d_out,
+                                   const int32_t *const *d_kp, int32_t n_neighbors, int32_t score_num,
+                                   int32_t score_den, int32_t *d_filtered, void *d_work, uint64_t work_bytes,
+                                   const int32_t *const *h_kp, const uint32_t *h_words, int32_t iterations,
+                                   int32_t thr, int32_t min_inliers, int32_t n_threads, int32_t *h_filtered,
+                                   int32_t *h_verified, void *stream);
+
 /* RANSAC global verification (Sec. 2.3.3) of each pair's matches on host
  * threads, with a 2D similarity as the two-view model (q = z (p - p_i) + q_i
  * in complex notation, fixed by two matches).  Host memory only.

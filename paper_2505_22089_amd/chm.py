@@ -70,7 +70,7 @@ EXPORTS = [
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_bruteforce_noalloc", "chm_schedule_mbr", "chm_schedule_from_steps", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
-    "chm_run_schedule_sao", "chm_ransac_filter",
+    "chm_run_schedule_sao", "chm_run_schedule_verify", "chm_ransac_filter",
 ]
 
 _lib = None
@@ -121,6 +121,8 @@ def lib():
             "chm_sao_filter_device": (i32, [i32, vp, vp, vp, i32, vp, vp, i32, i32, i32, vp, vp, vp, u64, vp]),
             "chm_run_schedule_sao": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, u64,
                                            vp]),
+            "chm_run_schedule_verify": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, u64,
+                                              vp, vp, i32, i32, i32, i32, vp, vp, vp]),
             "chm_ransac_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp]),
         }
         for name, (res, args) in sig.items():
@@ -479,6 +481,42 @@ def run_schedule_sao(store: Store, sched: Schedule, pairs: np.ndarray, descs: Se
                                       C.cast(kptr, C.c_void_p), n_neighbors, int(threshold[0]),
                                       int(threshold[1]), _dev_ptr(filtered), _dev_ptr(work),
                                       int(work.numel()), _stream(stream)))
+    return work
+
+
+def run_schedule_verify(store: Store, sched: Schedule, pairs: np.ndarray, descs: Sequence[np.ndarray],
+                        offs: np.ndarray, out, keypoints, host_keypoints, filtered, words: np.ndarray,
+                        h_filtered: np.ndarray, h_verified: np.ndarray, iterations: int = 64, thr: int = 64,
+                        min_inliers: int = 8, n_neighbors: int = 6, threshold=(1, 2), n_threads: int = 0,
+                        work=None, stream=None):
+    """run_schedule_sao plus RANSAC of every step on host threads beside the
+    device: h_filtered receives the SAO output and h_verified the verified
+    matches (host int32 arrays laid out like out; h_filtered best pinned).
+    Returns the SAO work tensor."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    keep = [np.ascontiguousarray(d, dtype=np.uint8) for d in descs]
+    parr = (C.c_void_p * len(keep))(*[k.ctypes.data for k in keep])
+    ns = np.ascontiguousarray([k.shape[0] for k in keep], dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    kptr = (C.c_void_p * len(keypoints))(*[_dev_ptr(k) for k in keypoints])
+    hk = [np.ascontiguousarray(k, dtype=np.int32) for k in host_keypoints]
+    hptr = (C.c_void_p * len(hk))(*[k.ctypes.data for k in hk])
+    words = np.ascontiguousarray(words, dtype=np.uint32)
+    for a in (h_filtered, h_verified):
+        if a.dtype != np.int32 or not a.flags.c_contiguous or a.size < int(offs[-1]):
+            raise ValueError("host outputs must be contiguous int32 arrays laid out like out")
+    if work is None:
+        import torch
+        nmax = int(max((ns[q] for q in pairs[:, 0]), default=1))
+        work = torch.empty(sao_work_bytes(len(pairs), nmax) + 256, dtype=torch.uint8, device=out.device)
+        work = work[(-work.data_ptr()) % 256:]
+    _check(lib().chm_run_schedule_verify(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
+                                         _np_ptr(ns), len(keep), _np_ptr(offs), _dev_ptr(out),
+                                         C.cast(kptr, C.c_void_p), n_neighbors, int(threshold[0]),
+                                         int(threshold[1]), _dev_ptr(filtered), _dev_ptr(work),
+                                         int(work.numel()), C.cast(hptr, C.c_void_p), _np_ptr(words),
+                                         int(iterations), int(thr), int(min_inliers), int(n_threads),
+                                         _np_ptr(h_filtered), _np_ptr(h_verified), _stream(stream)))
     return work
 
 

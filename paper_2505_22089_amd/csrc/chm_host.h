@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <map>
+#include <string>
 #include <unordered_map>
 #include <utility>
 #include <vector>
@@ -138,4 +139,12 @@ chm_status load_commit(chm_store* S, int32_t count, const int32_t* ids, const vo
 chm_status evict_hold(chm_store* S, int32_t count, const int32_t* ids,
                       std::vector<std::pair<uint64_t, uint64_t>>* held);
 void release_held(chm_store* S, std::vector<std::pair<uint64_t, uint64_t>>* held);
+// RANSAC (chm_ransac_filter's test) of the pairs idx[0..n) of a pair list on
+// host threads: pair p's matches and output rows start at h_starts[p] of
+// h_match / h_out, its words at h_words + p * iterations * 2.  The caller
+// has checked the arguments; returns an error message or "".
+std::string ransac_pairs(int32_t n, const int32_t* idx, const int32_t* h_pairs, const int32_t* const* h_kp,
+                         const int32_t* h_n_feats, const int64_t* h_starts, const int32_t* h_match,
+                         const uint32_t* h_words, int32_t iterations, int32_t thr, int32_t min_inliers,
+                         int32_t n_threads, int32_t* h_out);
 }  // namespace chm

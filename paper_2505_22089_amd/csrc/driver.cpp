@@ -7,7 +7,11 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <condition_variable>
+#include <deque>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "chm.h"
@@ -24,6 +28,95 @@ struct SaoStep {
   int32_t* d_filtered;
   void* d_work;
   uint64_t work_bytes;
+};
+
+// RANSAC of every step on host threads, beside the device: the step's SAO
+// output is copied to h_filtered (pinned host memory, laid out like d_out)
+// on a stream of the worker's own once the step's device work ends, then
+// RANSAC writes the step's verified matches to h_verified.
+struct VerifyStep {
+  const int32_t* const* h_kp;
+  const uint32_t* h_words;
+  int32_t iterations, thr, min_inliers, n_threads;
+  int32_t* h_filtered;
+  int32_t* h_verified;
+};
+
+// The worker thread: takes (step, event marking the end of its device
+// work) in step order, copies the step's filtered rows (runs of adjacent
+// output ranges, one copy each) and verifies its pairs.  The first error is
+// kept; finish() waits for every queued step.
+struct VerifyWorker {
+  const VerifyStep* v;
+  const int32_t* h_pairs;
+  const int32_t* h_n_feats;
+  const int64_t* h_offs;
+  const int32_t* d_filtered;
+  hipStream_t ds = nullptr;
+  std::thread th;
+  std::mutex mu;
+  std::condition_variable cv;
+  std::deque<std::pair<std::vector<int32_t>, hipEvent_t>> q;
+  bool closing = false;
+  std::string err;
+
+  void run() {
+    for (;;) {
+      std::pair<std::vector<int32_t>, hipEvent_t> job;
+      {
+        std::unique_lock<std::mutex> lk(mu);
+        cv.wait(lk, [&] { return closing || !q.empty(); });
+        if (q.empty()) return;
+        job = std::move(q.front());
+        q.pop_front();
+      }
+      std::vector<int32_t>& pp = job.first;
+      std::string e;
+      if (hipStreamWaitEvent(ds, job.second, 0) != hipSuccess) e = "verify: stream wait failed";
+      std::vector<int32_t> by(pp);
+      std::sort(by.begin(), by.end(), [&](int32_t a, int32_t b) { return h_offs[a] < h_offs[b]; });
+      for (size_t i = 0; e.empty() && i < by.size();) {
+        const int64_t s0 = h_offs[by[i]];
+        int64_t s1 = s0 + h_n_feats[h_pairs[2 * by[i]]];
+        size_t j = i + 1;
+        while (j < by.size() && h_offs[by[j]] == s1) s1 += h_n_feats[h_pairs[2 * by[j++]]];
+        if (s1 > s0 && hipMemcpyAsync(v->h_filtered + s0, d_filtered + s0, (size_t)(s1 - s0) * 4,
+                                      hipMemcpyDeviceToHost, ds) != hipSuccess)
+          e = "verify: copy failed";
+        i = j;
+      }
+      if (e.empty() && hipStreamSynchronize(ds) != hipSuccess) e = "verify: step's device work failed";
+      (void)hipEventDestroy(job.second);
+      if (e.empty() && !pp.empty())
+        e = ransac_pairs((int32_t)pp.size(), pp.data(), h_pairs, v->h_kp, h_n_feats, h_offs, v->h_filtered,
+                         v->h_words, v->iterations, v->thr, v->min_inliers, v->n_threads, v->h_verified);
+      if (!e.empty()) {
+        std::lock_guard<std::mutex> lk(mu);
+        if (err.empty()) err = e;
+      }
+    }
+  }
+  void push(std::vector<int32_t> pp, hipEvent_t ev) {
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      q.emplace_back(std::move(pp), ev);
+    }
+    cv.notify_one();
+  }
+  void finish() {
+    if (!th.joinable()) return;
+    {
+      std::lock_guard<std::mutex> lk(mu);
+      closing = true;
+    }
+    cv.notify_one();
+    th.join();
+  }
+  ~VerifyWorker() {
+    finish();
+    for (auto& j : q) (void)hipEventDestroy(j.second);
+    if (ds) (void)hipStreamDestroy(ds);
+  }
 };
 
 // What queued work may still read: the plans of the last two steps and the
@@ -53,7 +146,7 @@ struct InFlight {
 
 chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P,
                         const void* const* h_descs, const int32_t* h_n_feats, const int64_t* h_offs,
-                        int32_t* d_out, void* stream, const SaoStep* sao) {
+                        int32_t* d_out, void* stream, const SaoStep* sao, const VerifyStep* verify = nullptr) {
   if (!S || !sc) return fail(CHM_E_INVALID_ARG, "NULL argument");
   if (P < 0 || (P && (!h_pairs || !h_offs)) || !h_descs || !h_n_feats)
     return fail(CHM_E_INVALID_ARG, "bad arguments");
@@ -95,6 +188,18 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
   //   held until step k's end event; when the arena has no other room for
   //   step k+1's images, the host waits for that event and frees them first;
   // - s waits for step k+1's copies before it hashes the new images.
+  // declared before the streams and plans it reads, so it is joined first
+  VerifyWorker vw;
+  if (verify) {
+    vw.v = verify;
+    vw.h_pairs = h_pairs;
+    vw.h_n_feats = h_n_feats;
+    vw.h_offs = h_offs;
+    vw.d_filtered = sao->d_filtered;
+    if (hipStreamCreateWithFlags(&vw.ds, hipStreamNonBlocking) != hipSuccess)
+      return fail(CHM_E_HIP, "stream creation failed");
+    vw.th = std::thread([&vw] { vw.run(); });
+  }
   InFlight fl(S, s);
   if (hipStreamCreateWithFlags(&fl.xs, hipStreamNonBlocking) != hipSuccess)
     return fail(CHM_E_HIP, "stream creation failed");
@@ -179,6 +284,14 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
                                    nullptr, sao->d_work, s);
       if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
     }
+    if (verify && n > 0) {
+      hipEvent_t ve = nullptr;
+      if (hipEventCreateWithFlags(&ve, hipEventDisableTiming) != hipSuccess || hipEventRecord(ve, s) != hipSuccess) {
+        if (ve) (void)hipEventDestroy(ve);
+        return fail(CHM_E_HIP, "event record failed");
+      }
+      vw.push(std::vector<int32_t>(pp, pp + npp), ve);
+    }
     if (hipEventRecord(fl.ev[cur], s) != hipSuccess) return fail(CHM_E_HIP, "event record failed");
     // Step k-1 has ended: its plan and the slots evicted at step k (last
     // read by step k-1) are free.
@@ -193,6 +306,10 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
   }
   hipError_t e = hipStreamSynchronize(s);
   if (e != hipSuccess) return fail(CHM_E_HIP, "schedule run failed: %s", hipGetErrorString(e));
+  if (verify) {
+    vw.finish();
+    if (!vw.err.empty()) return fail(CHM_E_INVALID_ARG, "%s", vw.err.c_str());
+  }
   return CHM_OK;
 }
 
@@ -205,13 +322,11 @@ extern "C" chm_status chm_run_schedule(chm_store* S, const chm_schedule* sc, con
   return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, nullptr);
 }
 
-extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
-                                           int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
-                                           int32_t n_images, const int64_t* h_offs, int32_t* d_out,
-                                           const int32_t* const* d_kp, int32_t n_neighbors, int32_t score_num,
-                                           int32_t score_den, int32_t* d_filtered, void* d_work,
-                                           uint64_t work_bytes, void* stream) {
-  clear_error();
+static chm_status run_schedule_sao(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P,
+                                   const void* const* h_descs, const int32_t* h_n_feats, int32_t n_images,
+                                   const int64_t* h_offs, int32_t* d_out, const int32_t* const* d_kp,
+                                   int32_t n_neighbors, int32_t score_num, int32_t score_den, int32_t* d_filtered,
+                                   void* d_work, uint64_t work_bytes, void* stream, const VerifyStep* verify) {
   if (!d_kp || !h_n_feats || !d_filtered || !d_work || d_filtered == d_out)
     return fail(CHM_E_INVALID_ARG, "bad SAO buffers");
   if (n_neighbors < 1 || n_neighbors > kSaoMaxNeighbors)
@@ -225,13 +340,45 @@ extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc,
       return fail(CHM_E_INVALID_ARG, "pair %d names an image outside 0..%d", p, n_images - 1);
     if ((h_n_feats[q] > 0 && !d_kp[q]) || (h_n_feats[d] > 0 && !d_kp[d]))
       return fail(CHM_E_INVALID_ARG, "pair %d: NULL keypoints", p);
+    if (verify && ((h_n_feats[q] > 0 && !verify->h_kp[q]) || (h_n_feats[d] > 0 && !verify->h_kp[d])))
+      return fail(CHM_E_INVALID_ARG, "pair %d: NULL host keypoints", p);
     n_max = std::max(n_max, h_n_feats[q]);
   }
   if (work_bytes < sao_work_bytes(P, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
   const hipError_t e = launch_fill_u32(static_cast<uint32_t*>(d_work), 0u, 1, (hipStream_t)stream);
   if (e != hipSuccess) return fail(CHM_E_HIP, "%s", hipGetErrorString(e));
   const SaoStep sao{d_kp, n_neighbors, score_num, score_den, d_filtered, d_work, work_bytes};
-  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao);
+  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao, verify);
+}
+
+extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
+                                           int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
+                                           int32_t n_images, const int64_t* h_offs, int32_t* d_out,
+                                           const int32_t* const* d_kp, int32_t n_neighbors, int32_t score_num,
+                                           int32_t score_den, int32_t* d_filtered, void* d_work,
+                                           uint64_t work_bytes, void* stream) {
+  clear_error();
+  return run_schedule_sao(S, sc, h_pairs, P, h_descs, h_n_feats, n_images, h_offs, d_out, d_kp, n_neighbors,
+                          score_num, score_den, d_filtered, d_work, work_bytes, stream, nullptr);
+}
+
+extern "C" chm_status chm_run_schedule_verify(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
+                                              int32_t P, const void* const* h_descs, const int32_t* h_n_feats,
+                                              int32_t n_images, const int64_t* h_offs, int32_t* d_out,
+                                              const int32_t* const* d_kp, int32_t n_neighbors, int32_t score_num,
+                                              int32_t score_den, int32_t* d_filtered, void* d_work,
+                                              uint64_t work_bytes, const int32_t* const* h_kp,
+                                              const uint32_t* h_words, int32_t iterations, int32_t thr,
+                                              int32_t min_inliers, int32_t n_threads, int32_t* h_filtered,
+                                              int32_t* h_verified, void* stream) {
+  clear_error();
+  if (!h_kp || !h_filtered || !h_verified || (iterations > 0 && !h_words) || h_filtered == h_verified)
+    return fail(CHM_E_INVALID_ARG, "bad RANSAC buffers");
+  if (iterations < 0) return fail(CHM_E_INVALID_ARG, "negative iterations");
+  if (thr < 0 || thr >= (1 << 20)) return fail(CHM_E_INVALID_ARG, "thr must be 0..2^20-1");
+  const VerifyStep v{h_kp, h_words, iterations, thr, min_inliers, n_threads, h_filtered, h_verified};
+  return run_schedule_sao(S, sc, h_pairs, P, h_descs, h_n_feats, n_images, h_offs, d_out, d_kp, n_neighbors,
+                          score_num, score_den, d_filtered, d_work, work_bytes, stream, &v);
 }
 
 extern "C" chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t* out) {

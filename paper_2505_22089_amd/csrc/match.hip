@@ -36,6 +36,8 @@
 // once per item (skipped when consecutive items share the db image); db
 // images too large for the stage are read from their bucket-ordered code
 // copy, in the same launch.
+#include <atomic>
+
 #include "match_common.h"
 
 namespace chm {
@@ -487,14 +489,20 @@ template <int KT, int WG, bool LDSC, bool PERSIST>
 static hipError_t launch_one(const MatchArgs& a, int grid, hipStream_t s) {
   const size_t lds = LDSC ? (size_t)a.lds_top + kLdsTop : kMatchLdsTail;
   auto fn = k_match<KT, WG, LDSC, PERSIST>;
-  static int static_lds = -1;  // the code stage must start at LDS address 0
-  if (static_lds < 0) {
+  // The code stage must start at LDS address 0: the kernel may have no
+  // static LDS.  That is a property of the one code object (the same on
+  // every device), read once per process; concurrent first calls store the
+  // same value.
+  static std::atomic<int> static_lds{-1};
+  int sl = static_lds.load(std::memory_order_relaxed);
+  if (sl < 0) {
     hipFuncAttributes attr;
     hipError_t e = hipFuncGetAttributes(&attr, reinterpret_cast<const void*>(fn));
     if (e != hipSuccess) return e;
-    static_lds = (int)attr.sharedSizeBytes;
+    sl = (int)attr.sharedSizeBytes;
+    static_lds.store(sl, std::memory_order_relaxed);
   }
-  if (static_lds != 0) return hipErrorInvalidKernelFile;
+  if (sl != 0) return hipErrorInvalidKernelFile;
   {
     hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(fn),
                                        hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);

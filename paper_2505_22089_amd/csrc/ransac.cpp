@@ -28,6 +28,7 @@ constexpr int64_t kRansacCoordLimit = int64_t(1) << 19;
 constexpr int64_t kRansacThrLimit = int64_t(1) << 20;
 
 struct Job {
+  const int32_t* idx;       // job entry p is pair idx[p] of the lists below (null: p)
   const int32_t* pairs;
   const int32_t* const* kp;
   const int32_t* n_feats;
@@ -66,7 +67,8 @@ inline bool inlier(const Sim& s, const std::vector<int64_t>& P, const std::vecto
   return rx * rx + ry * ry <= lim;
 }
 
-std::string run_pair(const Job& J, int32_t p) {
+std::string run_pair(const Job& J, int32_t e) {
+  const int32_t p = J.idx ? J.idx[e] : e;
   const int32_t qi = J.pairs[2 * p], di = J.pairs[2 * p + 1];
   const int32_t nq = J.n_feats[qi], nd = J.n_feats[di];
   const int64_t o = J.offs[p];
@@ -120,6 +122,8 @@ std::string run_pair(const Job& J, int32_t p) {
   return std::string();
 }
 
+std::string run_jobs(const Job& J, int32_t n_pairs, int32_t n_threads);
+
 }  // namespace
 
 using chm::clear_error;
@@ -146,8 +150,24 @@ extern "C" chm_status chm_ransac_filter(int32_t n_pairs, const int32_t* h_pairs,
     if (h_offs[p] < 0 || h_offs[p + 1] - h_offs[p] != h_n_feats[q])
       return fail(CHM_E_INVALID_ARG, "pair %d: offsets do not span the query image's rows", p);
   }
-  const Job J{h_pairs, h_kp, h_n_feats, h_offs, h_match, h_words, iterations, thr, min_inliers, h_out,
+  const Job J{nullptr, h_pairs, h_kp, h_n_feats, h_offs, h_match, h_words, iterations, thr, min_inliers, h_out,
               h_best_counts};
+  const std::string err = run_jobs(J, n_pairs, n_threads);
+  if (!err.empty()) return fail(CHM_E_INVALID_ARG, "%s", err.c_str());
+  return CHM_OK;
+}
+
+std::string chm::ransac_pairs(int32_t n, const int32_t* idx, const int32_t* h_pairs, const int32_t* const* h_kp,
+                              const int32_t* h_n_feats, const int64_t* h_starts, const int32_t* h_match,
+                              const uint32_t* h_words, int32_t iterations, int32_t thr, int32_t min_inliers,
+                              int32_t n_threads, int32_t* h_out) {
+  const Job J{idx, h_pairs, h_kp, h_n_feats, h_starts, h_match, h_words, iterations, thr, min_inliers, h_out,
+              nullptr};
+  return run_jobs(J, n, n_threads);
+}
+
+namespace {
+std::string run_jobs(const Job& J, int32_t n_pairs, int32_t n_threads) {
   int T = n_threads > 0 ? n_threads : (int)std::thread::hardware_concurrency();
   T = std::max(1, std::min(T, n_pairs));
   std::atomic<int32_t> next{0};
@@ -168,6 +188,6 @@ extern "C" chm_status chm_ransac_filter(int32_t n_pairs, const int32_t* h_pairs,
   for (int t = 1; t < T; ++t) pool.emplace_back(worker);
   worker();
   for (auto& th : pool) th.join();
-  if (!err.empty()) return fail(CHM_E_INVALID_ARG, "%s", err.c_str());
-  return CHM_OK;
+  return err;
 }
+}  // namespace

@@ -67,14 +67,10 @@ def test_single_bucket_cascade_equals_bruteforce_on_gpu():
     A = synth.sift_like(rng, 400)
     B = np.concatenate([synth.noisy_copy(rng, A[:200]), synth.sift_like(rng, 200)])
     W = synth.projection_weights(42, 128)
-    wl = synth.Workload(name="t", images=[A, B], pairs=np.array([[0, 1]], np.int32), W=W,
-                        mu=synth.centring_vector([A, B]), L=1, m=0, K=32)
-    st = new_store(wl)
-    load_all(st, wl.images)
-    # K = 32 < 400 candidates: not exhaustive; use the brute-force equivalence only
-    # through the oracle for K >= N on a small db
-    small = synth.Workload(name="t2", images=[A[:30], B[:30]], pairs=wl.pairs, W=W, mu=wl.mu,
-                           L=1, m=0, K=32)
+    # with one table of one bucket and K = 32 >= the db's 30 points, cascade
+    # hashing re-ranks every db point: exhaustive 2-NN
+    small = synth.Workload(name="t2", images=[A[:30], B[:30]], pairs=np.array([[0, 1]], np.int32), W=W,
+                           mu=synth.centring_vector([A, B]), L=1, m=0, K=32)
     st2 = new_store(small)
     load_all(st2, small.images)
     out, _, _ = run_match(st2, [(0, 1)])

@@ -168,3 +168,56 @@ def test_schedule_with_sao_per_block_row():
     ref, _, _, _ = O.match_pairs(H, wl.pairs, wl.L, wl.m, wl.K, wl.ratio)
     assert np.array_equal(o, ref)
     assert np.array_equal(filt.cpu().numpy(), chm.sao_filter(kps, wl.pairs, offs, o, 6, (1, 2)))
+
+
+def test_schedule_with_sao_and_ransac_per_block_row():
+    """An MBR schedule under a binding cap with the device SAO after every
+    step and RANSAC of every step on host threads beside the device: the SAO
+    output copied to the host equals the device's, the verified matches equal
+    host RANSAC of it on every pair, and on sampled pairs the oracle chain
+    (oracle matches, then oracle SAO, then oracle RANSAC)."""
+    from oracle import oracle as O
+    from oracle import ransac as OR
+    from oracle import sao as OS
+    from tests.gpu_helpers import device
+    wl = synth.config5(rows=5, cols=16, n_feats=1200)
+    kps = synth.keypoints(wl)
+    n = len(wl.images)
+    cfg = chm.config(L=wl.L, m=wl.m, K=wl.K, ratio=wl.ratio)
+    sizes = [chm.image_bytes(cfg, x.shape[0]) + 256 for x in wl.images]
+    cap = 24 * sizes[0]
+    sched = chm.schedule_mbr(n, wl.pairs, sizes, cap, 8, keep_handle=True)
+    assert len(sched.steps) > 2
+    arena = torch.empty(chm.store_overhead_bytes(cfg) + cap + (16 << 20), dtype=torch.uint8, device=device())
+    st = chm.Store(cfg, wl.W, wl.mu, arena)
+    offs = np.zeros(len(wl.pairs) + 1, np.int64)
+    offs[1:] = np.cumsum([wl.images[q].shape[0] for q in wl.pairs[:, 0]])
+    total = int(offs[-1])
+    out = torch.full((total,), -7, dtype=torch.int32, device=device())
+    filt = torch.full_like(out, -7)
+    iters, thr, min_in = 32, 64, 8
+    words = synth.ransac_words(len(wl.pairs), iters)
+    h_filt = torch.full((total,), -7, dtype=torch.int32).pin_memory().numpy()
+    h_ver = np.full(total, -7, np.int32)
+    work = chm.run_schedule_verify(st, sched, wl.pairs, wl.images, offs, out, [_dev(k) for k in kps], kps, filt,
+                                   words, h_filt, h_ver, iterations=iters, thr=thr, min_inliers=min_in)
+    torch.cuda.synchronize()
+    assert chm.sao_input_errors(work) == 0
+    chm.schedule_free(sched)
+    st.close()
+    f = filt.cpu().numpy()
+    assert np.array_equal(h_filt, f)
+    ref_v, _ = chm.ransac_filter(kps, wl.pairs, offs, f, words, thr, min_in)
+    assert np.array_equal(h_ver, ref_v)
+    assert (h_ver >= 0).any() and (h_ver >= 0).sum() < (f >= 0).sum() + 1
+    # the oracle chain on sampled pairs
+    idx = sorted(np.random.default_rng(2).choice(len(wl.pairs), 4, replace=False).tolist())
+    need = sorted({int(i) for i in wl.pairs[idx].ravel()})
+    H = O.hash_workload(wl, need)
+    ref_m, so, _, _ = O.match_pairs(H, wl.pairs[idx], wl.L, wl.m, wl.K, wl.ratio)
+    for k, p in enumerate(idx):
+        q, d = wl.pairs[p]
+        m = ref_m[so[k]:so[k + 1]]
+        _, s_out = OS.sao_pair(kps[q], kps[d], m, 6, (1, 2))
+        v_out, _ = OR.ransac_pair(kps[q], kps[d], s_out, words[p], thr, min_in)
+        assert np.array_equal(h_ver[offs[p]:offs[p + 1]], v_out), p
