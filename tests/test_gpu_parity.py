@@ -315,3 +315,32 @@ def test_match_parity_stored_golden_pair():
         out, _, _ = run_match(st, [(0, 1)], mode)
         assert np.array_equal(out, expect)
         st.close()
+
+
+@pytest.mark.parametrize("seed", range(12))
+def test_random_configurations(seed):
+    """Seeded random configurations (tables, bucket bits, K, ratio, both
+    flags, image sizes including empty and one-feature images, self pairs),
+    both match kernels and both modes, against the oracle's matches and
+    top-K keys."""
+    rng = np.random.default_rng(1000 + seed)
+    L = int(rng.integers(1, 9))
+    m = int(rng.integers(0, 9))
+    K = int(rng.choice([1, 2, 3, 5, 8, 13, 16, 32]))
+    num = int(rng.integers(1, 100))
+    den = int(rng.integers(num, 101))
+    sizes = [int(rng.choice([0, 1, 2, 63, 64, 65, 300, 1000, 2500])) for _ in range(4)]
+    wl = small_workload(sizes, seed=seed, L=L, m=m, K=K, copies=float(rng.uniform(0.1, 0.6)))
+    wl.ratio = (num, den)
+    accept = bool(rng.integers(0, 2))
+    whole = bool(rng.integers(0, 2))
+    st = new_store(wl, accept_single=accept, whole_last_bucket=whole)
+    if rng.integers(0, 2):
+        st.set_tuning(queries_per_item=int(rng.choice([64, 256, 1024, 3072])),
+                      wg_threads=int(rng.choice([256, 1024])), lds_codes=int(rng.integers(0, 2)),
+                      group_queries=int(rng.choice([1, 2000, 98304])))
+    load_all(st, wl.images)
+    pairs = [(int(q), int(d)) for q, d in rng.integers(0, 4, size=(6, 2))]
+    for mode in (chm.MATCH_BATCHED, chm.MATCH_PLAIN):
+        check_matches(st, wl, pairs, mode, K)
+    st.close()
