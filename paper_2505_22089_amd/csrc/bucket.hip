@@ -30,7 +30,7 @@
 
 namespace chm {
 
-constexpr int kBucketWG = 512;
+constexpr int kBucketWG = 1024;
 constexpr int kBucketWaves = kBucketWG / 64;
 constexpr int kBucketMaxN = 65536;
 

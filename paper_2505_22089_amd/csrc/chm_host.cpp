@@ -130,9 +130,8 @@ static const uint64_t kHdrCmu = kHdrTau + round_up(3 * kRowsPad * 4, 256);
 static const uint64_t kHdrMu = kHdrCmu + round_up(kRowsPad * 8, 256);
 static const uint64_t kHdrFix = kHdrMu + 256;
 static const uint64_t kHdrFixList = kHdrFix + 256;
-// fix-up list: overflow word, per-wave counts, regions
-static const uint64_t kHdrBytes =
-    kHdrFixList + round_up(((uint64_t)kFixListCap + 1 + (uint64_t)kMaxProjWaves) * 4, 256);
+// fix-up list: one region per projection wavefront
+static const uint64_t kHdrBytes = kHdrFixList + round_up((uint64_t)kFixListCap * 4, 256);
 
 extern "C" chm_status chm_store_overhead_bytes(const chm_config* cfg, uint64_t* out) {
   clear_error();
@@ -248,8 +247,6 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   if (e == hipSuccess) e = hipMemcpy(S->dMu, h_mu, kDim, hipMemcpyHostToDevice);
   unsigned long long zero[2] = {0, 0};  // fix-ups, flips
   if (e == hipSuccess) e = hipMemcpy(S->dFix, zero, sizeof zero, hipMemcpyHostToDevice);
-  // the fix-up list's overflow word: no batch (batch numbers start at 1)
-  if (e == hipSuccess) e = hipMemcpy(S->dFixList, zero, 4, hipMemcpyHostToDevice);
   if (e == hipSuccess) e = hipStreamCreateWithFlags(&S->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete S;
@@ -290,7 +287,6 @@ chm_status chm::hash_images(chm_store* S, const std::vector<const ImageSlot*>& s
     hb.arena = S->base;
     hb.L = S->cfg.num_tables;
     hb.m = S->cfg.bucket_bits;
-    hb.seq = ++S->hash_seq == 0 ? ++S->hash_seq : S->hash_seq;  // never 0 (the word's initial value)
     int cnt = 0, tiles = 0;
     int descs = 0;
     for (size_t i = i0; i < slots.size() && cnt < kHashBatch; ++i, ++cnt) {

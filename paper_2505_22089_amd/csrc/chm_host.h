@@ -60,7 +60,6 @@ struct chm_store {
   int lds_top = 0;  // byte address of the match kernel's LDS control words
   int device = 0;
   hipStream_t cap_stream = nullptr;
-  uint32_t hash_seq = 0;  // number of the last hash batch (its fix-up overflow mark)
 };
 
 struct chm_plan {

@@ -9,7 +9,6 @@ namespace chm {
 constexpr int kDim = 128;
 constexpr int kCodeWords = 4;   // 128-bit long code as 4 x u32
 constexpr int kRowsPad = 192;   // projection rows padded: 128 code + up to 64 bucket bits
-constexpr int kWStride = 136;   // bf16 elements per projection row in LDS (272 B: spreads banks)
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
 // Device-side view of one resident image.
@@ -204,8 +203,6 @@ struct HashBatch {
   int32_t count;
   int32_t L;
   int32_t m;
-  uint32_t seq;             // the store's batch number (nonzero): the fix-up
-                            // list's overflow word holds it when this batch overflowed
 };
 
 __host__ __device__ inline HashImage hash_image_at(uint8_t* base, int n, int L, int m) {
@@ -236,9 +233,8 @@ struct ProjConsts {
   const double* cmu;        // kRowsPad: W_r . mu, exact
   const uint8_t* mu;        // 128
   unsigned long long* fixups;  // running counts: [0] fp64 recomputes, [1] bits they changed
-  uint32_t* fixlist;        // [0] overflow word (the seq of the last batch that
-                            // overflowed), [1..n_waves] per-wave counts, then
-                            // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d)
+  uint32_t* fixlist;        // n_waves regions of fix_cap/n_waves entries (im<<24 | r<<16 | d),
+                            // one per projection wavefront
   uint32_t fix_cap;         // entries the list holds
   int32_t n_waves;          // projection wavefronts of the launch (set by launch_project)
   int32_t R;                // 128 + L*m
