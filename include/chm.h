@@ -301,7 +301,7 @@ chm_status chm_bruteforce(const uint8_t *d_q, int32_t nq, const uint8_t *d_d, in
  * ends) instead of a caller buffer.  It allocates nothing and calls no
  * hipMalloc/hipFree.  Sizes whose chm_bruteforce_work_bytes exceed 32 MiB
  * (about 2 million queries at one db split; a 40,000 x 40,000 pair needs
- * 4.5 MB) are rejected with CHM_E_CAPACITY.  All calls on one GPU share that
+ * 9.1 MB) are rejected with CHM_E_CAPACITY.  All calls on one GPU share that
  * array: calls that overlap in time on one GPU (other streams, other host
  * threads) race and give undefined results; calls ordered on one stream are
  * safe.  The first call on a device resolves its copy of the array. */

@@ -265,6 +265,7 @@ hipError_t launch_match_bm(const BmArgs& a, int K, int grid, hipStream_t s);
 hipError_t launch_bruteforce(const uint8_t* q, int nq, const uint8_t* d, int nd, int ra, int rb,
                              int32_t* out, void* work, int splits, hipStream_t s);
 int bruteforce_splits(int nq, int nd);
+uint64_t bruteforce_work_bytes(int nq, int nd);
 // The library's own brute-force workspace (chm_bruteforce_noalloc): a static
 // device array of kBfScratchBytes per GPU; bruteforce_scratch() returns the
 // current device's copy (resolved once per device, kept until the process

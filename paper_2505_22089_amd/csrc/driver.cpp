@@ -385,7 +385,7 @@ extern "C" chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t
   clear_error();
   if (!out || nq < 0 || nd < 0 || nq >= (1 << 24) || nd >= (1 << 24))
     return fail(CHM_E_INVALID_ARG, "bad arguments");
-  const uint64_t b = (uint64_t)bruteforce_splits(nq, nd) * (uint64_t)nq * 16u;
+  const uint64_t b = bruteforce_work_bytes(nq, nd);
   *out = b < 256 ? 256 : b;
   return CHM_OK;
 }

@@ -93,19 +93,23 @@ __device__ __forceinline__ uint32_t push_sign(uint32_t word, float v, uint32_t s
 // c_r = W_r . mu; four independent partial sums keep each exact.  W is
 // read from LDS (row-major bf16).
 __device__ __forceinline__ double exact_projection_lds(const uint8_t* xr, const uint16_t* sWr, double c) {
+  u32x4 xv[8];  // the whole row first: one memory round trip
+#pragma unroll
+  for (int k16 = 0; k16 < kDim / 16; ++k16) xv[k16] = *(gcu32x4*)(xr + 16 * k16);
   double p0 = 0.0, p1 = 0.0, p2 = 0.0, p3 = 0.0;
-#pragma unroll 2
+#pragma unroll
   for (int k16 = 0; k16 < kDim / 16; ++k16) {
-    const u32x4 xv = *(gcu32x4*)(xr + 16 * k16);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
       const uint2 wv = *reinterpret_cast<const uint2*>(sWr + 16 * k16 + 4 * q);
-      const uint32_t x4 = xv[q];
+      const uint32_t x4 = xv[k16][q];
       p0 = fma((double)__uint_as_float(wv.x << 16), (double)(x4 & 0xFF), p0);
       p1 = fma((double)__uint_as_float(wv.x & 0xFFFF0000u), (double)((x4 >> 8) & 0xFF), p1);
       p2 = fma((double)__uint_as_float(wv.y << 16), (double)((x4 >> 16) & 0xFF), p2);
       p3 = fma((double)__uint_as_float(wv.y & 0xFFFF0000u), (double)(x4 >> 24), p3);
     }
+    // keep the scheduler from hoisting every LDS read and conversion of W
+    __builtin_amdgcn_sched_barrier(0);
   }
   return ((p0 + p1) + (p2 + p3)) - c;
 }
