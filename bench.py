@@ -366,6 +366,19 @@ def sao_leg(wl, out_b, offs, stream, reps=10, n_neighbors=6, threshold=(1, 2), h
     t0 = time.perf_counter()
     v, _ = chm.ransac_filter(kps, wl.pairs[:P], offs[:P + 1], g[:end], words, 64, 8, n_threads=threads)
     ransac_s = time.perf_counter() - t0
+    # and on the device, over all pairs (the same words for the host's pairs)
+    dwords = torch.from_numpy(synth.ransac_words(len(wl.pairs), 64).view(np.int32)).to(out_b.device)
+    d_ver = torch.empty_like(out_b)
+    with torch.cuda.stream(stream):
+        rwork = chm.ransac_filter_device(d_kps, wl.pairs, offs, d_out, d_ver, dwords, 64, 8, stream=stream)
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            chm.ransac_filter_device(d_kps, wl.pairs, offs, d_out, d_ver, dwords, 64, 8, work=rwork, stream=stream)
+        b.record(stream)
+    stream.synchronize()
+    rdev_ms = a.elapsed_time(b) / reps
+    dv = d_ver.cpu().numpy()
     return {"n_neighbors": n_neighbors, "threshold": "%d/%d" % threshold,
             "device_ms": round(dev_ms, 4), "device_pairs_per_s": round(len(wl.pairs) / (dev_ms * 1e-3), 1),
             "matches_in": int((m >= 0).sum()), "kept": int((g >= 0).sum()), "input_errors": bad,
@@ -373,7 +386,10 @@ def sao_leg(wl, out_b, offs, stream, reps=10, n_neighbors=6, threshold=(1, 2), h
             "host_pairs_per_s": round(P / host_s, 1),
             "device_equals_host": bool(np.array_equal(g[:end], h)),
             "ransac_host_ms": round(ransac_s * 1e3, 1), "ransac_host_pairs_per_s": round(P / ransac_s, 1),
-            "ransac_verified": int((v >= 0).sum())}
+            "ransac_verified": int((v >= 0).sum()),
+            "ransac_device_ms": round(rdev_ms, 4), "ransac_device_pairs_per_s": round(len(wl.pairs) / (rdev_ms * 1e-3), 1),
+            "ransac_device_equals_host": bool(np.array_equal(dv[:end], v)),
+            "ransac_device_input_errors": chm.sao_input_errors(rwork)}
 
 
 def bruteforce_leg(wl, descs, stream, reps=5):
@@ -497,7 +513,24 @@ def run_grid(args):
                 "ransac": "64 hypotheses, 4 px (64 units), at least 8 inliers",
                 "input_errors": chm.sao_input_errors(work)}
             say("cap %.0f GB with SAO + RANSAC: %.3f s, %.0f pairs/s" % (cap_gb, wall_v, P / wall_v))
-            del d_kps, work, filt, h_filt, h_ver
+            # and with the RANSAC on the device too (the same words)
+            store.close()
+            store = chm.Store(cfg, wl.W, wl.mu, arena)
+            d_ver = torch.empty_like(out)
+            d_words = torch.from_numpy(words.view(np.int32)).to(dev)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            work, rwork = chm.run_schedule_verify_device(store, sched, wl.pairs, views, offs, out, d_kps, filt, d_ver,
+                                                         d_words, iterations=64, thr=64, min_inliers=8)
+            torch.cuda.synchronize()
+            wall_d = time.perf_counter() - t0
+            dv = d_ver.cpu().numpy()
+            runs[-1]["with_device_sao_device_ransac"] = {
+                "seconds": round(wall_d, 4), "pairs_per_s": round(P / wall_d, 1), "verified": int((dv >= 0).sum()),
+                "equals_host_ransac": bool(np.array_equal(dv, h_ver)),
+                "input_errors": chm.sao_input_errors(work) + chm.sao_input_errors(rwork)}
+            say("cap %.0f GB with SAO + device RANSAC: %.3f s, %.0f pairs/s" % (cap_gb, wall_d, P / wall_d))
+            del d_kps, work, rwork, filt, h_filt, h_ver, d_ver, d_words
         chm.schedule_free(sched)
         store.close()
         del arena

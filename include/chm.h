@@ -502,6 +502,54 @@ chm_status chm_ransac_filter(int32_t n_pairs, const int32_t *h_pairs, const int3
                              int32_t thr, int32_t min_inliers, int32_t n_threads, int32_t *h_out,
                              int32_t *h_best_counts);
 
+/* RANSAC on the device: the verification of chm_ransac_filter (Sec. 2.3.3;
+ * the same hypotheses from the same words, the same exact integer test, the
+ * same verified matches and best counts), one work-group per pair.
+ *   d_kp         : host array of n_images device pointers; d_kp[img] holds
+ *                  h_n_feats[img] x 2 int32 keypoints, |x|, |y| < 2^19.
+ *   h_pairs, h_n_feats, h_offs : as in chm_ransac_filter (host memory).
+ *   d_match      : device matches laid out by h_offs.
+ *   d_words      : device n_pairs x iterations x 2 uint32 (the caller's
+ *                  generator), as h_words of chm_ransac_filter.
+ *   iterations, thr, min_inliers : as in chm_ransac_filter.
+ *   d_out        : device verified matches; may be d_match itself.
+ *   d_best_counts: optional device int32 per pair (best inlier count).
+ *   d_work       : 256-byte aligned device scratch of chm_ransac_work_bytes
+ *                  (n_pairs, largest query image) bytes (CHM_E_CAPACITY if
+ *                  smaller).  When the work completes, its first int32
+ *                  holds the number of pairs whose input broke the contract
+ *                  (a db row outside the db image, a coordinate out of
+ *                  range): such pairs verify nothing, where the host call
+ *                  fails instead.
+ * The call uploads the pair list (synchronising `stream` once) and then
+ * enqueues the kernel on `stream`. */
+chm_status chm_ransac_work_bytes(int32_t n_pairs, int32_t max_query_rows, uint64_t *out_bytes);
+chm_status chm_ransac_filter_device(int32_t n_pairs, const int32_t *h_pairs, const int32_t *const *d_kp,
+                                    const int32_t *h_n_feats, int32_t n_images, const int64_t *h_offs,
+                                    const int32_t *d_match, const uint32_t *d_words, int32_t iterations,
+                                    int32_t thr, int32_t min_inliers, int32_t *d_out, int32_t *d_best_counts,
+                                    void *d_work, uint64_t work_bytes, void *stream);
+
+/* chm_run_schedule_sao with device RANSAC of every block row on the same
+ * stream (Algorithm 1's outlier removal entirely on the device): after each
+ * step's matching and SAO, chm_ransac_filter_device's verification of the
+ * step's pairs reads d_filtered and writes d_verified (laid out like d_out).
+ *   d_words, iterations, thr, min_inliers : as in chm_ransac_filter_device,
+ *                  d_words indexed by the pair's position in h_pairs.
+ *   d_rwork      : 256-byte aligned, chm_ransac_work_bytes(n_pairs, largest
+ *                  query image) bytes; its first int32 counts, over the
+ *                  whole run, the pairs whose RANSAC input broke the
+ *                  contract.
+ * Other arguments as in chm_run_schedule_sao (d_work is the SAO's). */
+chm_status chm_run_schedule_verify_device(chm_store *store, const chm_schedule *s, const int32_t *h_pairs,
+                                          int32_t n_pairs, const void *const *h_descs, const int32_t *h_n_feats,
+                                          int32_t n_images, const int64_t *h_out_offsets, int32_t *d_out,
+                                          const int32_t *const *d_kp, int32_t n_neighbors, int32_t score_num,
+                                          int32_t score_den, int32_t *d_filtered, void *d_work,
+                                          uint64_t work_bytes, const uint32_t *d_words, int32_t iterations,
+                                          int32_t thr, int32_t min_inliers, int32_t *d_verified, void *d_rwork,
+                                          uint64_t rwork_bytes, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,7 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libchm.so")
-SOURCES = ["chm_host.cpp", "sched.cpp", "driver.cpp", "sao.cpp", "ransac.cpp", "sao_device.hip", "project.hip", "bucket.hip", "match.hip", "match_bm.hip",
+SOURCES = ["chm_host.cpp", "sched.cpp", "driver.cpp", "sao.cpp", "ransac.cpp", "sao_device.hip", "ransac_device.hip", "project.hip", "bucket.hip", "match.hip", "match_bm.hip",
            "bruteforce.hip"]
 ARCH = "gfx950"
 

@@ -70,7 +70,8 @@ EXPORTS = [
     "chm_bruteforce_work_bytes", "chm_bruteforce", "chm_bruteforce_noalloc", "chm_schedule_mbr", "chm_schedule_from_steps", "chm_schedule_num_steps",
     "chm_schedule_step", "chm_schedule_info", "chm_schedule_free", "chm_gps_order",
     "chm_run_schedule", "chm_sao_filter", "chm_sao_work_bytes", "chm_sao_filter_device",
-    "chm_run_schedule_sao", "chm_run_schedule_verify", "chm_ransac_filter",
+    "chm_run_schedule_sao", "chm_run_schedule_verify", "chm_ransac_filter", "chm_ransac_work_bytes",
+    "chm_ransac_filter_device", "chm_run_schedule_verify_device",
 ]
 
 _lib = None
@@ -124,6 +125,11 @@ def lib():
             "chm_run_schedule_verify": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, u64,
                                               vp, vp, i32, i32, i32, i32, vp, vp, vp]),
             "chm_ransac_filter": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, i32, i32, vp, vp]),
+            "chm_ransac_work_bytes": (i32, [i32, i32, P(u64)]),
+            "chm_ransac_filter_device": (i32, [i32, vp, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp, vp, vp, u64,
+                                               vp]),
+            "chm_run_schedule_verify_device": (i32, [vp, vp, vp, i32, vp, vp, i32, vp, vp, vp, i32, i32, i32, vp,
+                                                     vp, u64, vp, i32, i32, i32, vp, vp, u64, vp]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -596,3 +602,68 @@ def ransac_filter(keypoints: Sequence[np.ndarray], pairs: np.ndarray, offs: np.n
                                    int(words.shape[1]), int(thr), int(min_inliers), n_threads,
                                    _np_ptr(out), _np_ptr(best)))
     return out, best
+
+
+def ransac_work_bytes(n_pairs: int, max_query_rows: int) -> int:
+    v = C.c_uint64()
+    _check(lib().chm_ransac_work_bytes(int(n_pairs), int(max_query_rows), C.byref(v)))
+    return int(v.value)
+
+
+def _aligned_work(nbytes: int, device):
+    import torch
+    w = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+    return w[(-w.data_ptr()) % 256:]
+
+
+def ransac_filter_device(keypoints, pairs: np.ndarray, offs: np.ndarray, match, out, words, thr: int,
+                         min_inliers: int = 8, best_counts=None, work=None, stream=None):
+    """RANSAC verification on the device: `keypoints[img]` a device (n, 2)
+    int32 tensor, `match`/`out` device int32 tensors laid out by `offs`
+    (`out` may be `match`), `words` a device uint32 tensor of shape
+    (n_pairs, iterations, 2), `best_counts` an optional device int32 tensor
+    per pair.  Returns the work tensor; its first int32 counts the pairs
+    whose input broke the contract."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    nf = np.array([0 if k is None else int(k.shape[0]) for k in keypoints], dtype=np.int32)
+    ptrs = (C.c_void_p * max(1, len(keypoints)))(*[0 if k is None else _dev_ptr(k) for k in keypoints])
+    iterations = int(words.shape[1]) if words.dim() == 3 else 0
+    if work is None:
+        nmax = int(max((nf[q] for q in pairs[:, 0]), default=1))
+        work = _aligned_work(ransac_work_bytes(len(pairs), nmax), match.device)
+    _check(lib().chm_ransac_filter_device(len(pairs), _np_ptr(pairs), C.cast(ptrs, C.c_void_p), _np_ptr(nf),
+                                          len(keypoints), _np_ptr(offs), _dev_ptr(match), _dev_ptr(words),
+                                          iterations, int(thr), int(min_inliers), _dev_ptr(out),
+                                          _dev_ptr(best_counts), _dev_ptr(work), int(work.numel()),
+                                          _stream(stream)))
+    return work
+
+
+def run_schedule_verify_device(store: "Store", sched: "Schedule", pairs: np.ndarray, descs: Sequence[np.ndarray],
+                               offs: np.ndarray, out, keypoints, filtered, verified, words, iterations: int = 64,
+                               thr: int = 64, min_inliers: int = 8, n_neighbors: int = 6, threshold=(1, 2),
+                               work=None, rwork=None, stream=None):
+    """run_schedule_sao plus device RANSAC of every step on the same stream:
+    `filtered` receives the SAO output and `verified` the verified matches
+    (device int32 tensors laid out like out); `words` a device uint32 tensor
+    (n_pairs, iterations, 2).  Returns (SAO work, RANSAC work)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.int32).reshape(-1, 2)
+    keep = [np.ascontiguousarray(d, dtype=np.uint8) for d in descs]
+    parr = (C.c_void_p * len(keep))(*[k.ctypes.data for k in keep])
+    ns = np.ascontiguousarray([k.shape[0] for k in keep], dtype=np.int32)
+    offs = np.ascontiguousarray(offs, dtype=np.int64)
+    kptr = (C.c_void_p * len(keypoints))(*[_dev_ptr(k) for k in keypoints])
+    nmax = int(max((ns[q] for q in pairs[:, 0]), default=1))
+    if work is None:
+        work = _aligned_work(sao_work_bytes(len(pairs), nmax), out.device)
+    if rwork is None:
+        rwork = _aligned_work(ransac_work_bytes(len(pairs), nmax), out.device)
+    _check(lib().chm_run_schedule_verify_device(store.handle, sched.handle, _np_ptr(pairs), len(pairs), parr,
+                                                _np_ptr(ns), len(keep), _np_ptr(offs), _dev_ptr(out),
+                                                C.cast(kptr, C.c_void_p), n_neighbors, int(threshold[0]),
+                                                int(threshold[1]), _dev_ptr(filtered), _dev_ptr(work),
+                                                int(work.numel()), _dev_ptr(words), int(iterations), int(thr),
+                                                int(min_inliers), _dev_ptr(verified), _dev_ptr(rwork),
+                                                int(rwork.numel()), _stream(stream)))
+    return work, rwork

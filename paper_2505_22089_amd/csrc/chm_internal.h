@@ -92,6 +92,20 @@ struct BmArgs {
   int32_t accept_single;
 };
 
+// Device RANSAC (ransac_device.hip), in the same two parts as the device
+// SAO: ransac_upload writes the pair table (word_pair[p], or p when null, is
+// the index of pair p's random words and best count) and returns once it
+// is on the device; ransac_run verifies table entries first..first+count-1
+// with at most n_max query rows each.  The work buffer's first int32
+// counts pairs whose input broke the contract.
+uint64_t ransac_work_bytes(int32_t n_pairs, int32_t max_rows);
+hipError_t ransac_upload(int32_t n_pairs, const int32_t* h_pairs, const int32_t* const* d_kp,
+                         const int32_t* h_n_feats, const int64_t* h_starts, const int32_t* word_pair,
+                         void* d_work, hipStream_t s);
+hipError_t ransac_run(int32_t first, int32_t count, int32_t table_pairs, int32_t n_max, const int32_t* d_match,
+                      const uint32_t* d_words, int32_t iterations, int32_t thr, int32_t min_inliers,
+                      int32_t* d_out, int32_t* d_best_counts, void* d_work, hipStream_t s);
+
 // Device SAO (sao_device.hip).  h_starts[p] is where pair p's query rows
 // begin in d_match / d_out / d_ced (only starts are read); the caller has
 // checked the arguments.  clear_errors zeroes the work buffer's error word.

@@ -30,6 +30,15 @@ struct SaoStep {
   uint64_t work_bytes;
 };
 
+// RANSAC of every step on the device, after its SAO on the same stream.
+struct RansacStep {
+  const uint32_t* d_words;
+  int32_t iterations, thr, min_inliers;
+  int32_t* d_verified;
+  void* d_work;
+  uint64_t work_bytes;
+};
+
 // RANSAC of every step on host threads, beside the device: the step's SAO
 // output is copied to h_filtered (pinned host memory, laid out like d_out)
 // on a stream of the worker's own once the step's device work ends, then
@@ -146,14 +155,15 @@ struct InFlight {
 
 chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P,
                         const void* const* h_descs, const int32_t* h_n_feats, const int64_t* h_offs,
-                        int32_t* d_out, void* stream, const SaoStep* sao, const VerifyStep* verify = nullptr) {
+                        int32_t* d_out, void* stream, const SaoStep* sao, const VerifyStep* verify = nullptr,
+                        const RansacStep* ransac = nullptr) {
   if (!S || !sc) return fail(CHM_E_INVALID_ARG, "NULL argument");
   if (P < 0 || (P && (!h_pairs || !h_offs)) || !h_descs || !h_n_feats)
     return fail(CHM_E_INVALID_ARG, "bad arguments");
   const int nsteps = chm_schedule_num_steps(sc);
   // The schedule's pairs in step order: step k matches entries
   // first[k] .. first[k+1]-1 of (sp, starts).
-  std::vector<int32_t> sp, first(nsteps + 1, 0), rows(nsteps, 1);
+  std::vector<int32_t> sp, first(nsteps + 1, 0), rows(nsteps, 1), orig;
   std::vector<int64_t> starts;
   for (int k = 0; k < nsteps; ++k) {
     const int32_t *ev, *ld, *pp;
@@ -166,6 +176,7 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
       sp.push_back(h_pairs[2 * p]);
       sp.push_back(h_pairs[2 * p + 1]);
       starts.push_back(h_offs[p]);
+      orig.push_back(p);
       rows[k] = std::max(rows[k], h_n_feats[h_pairs[2 * p]]);
     }
     first[k + 1] = (int32_t)starts.size();
@@ -177,6 +188,14 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
     if (sao->work_bytes < sao_work_bytes(total, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
     const hipError_t e = sao_upload(total, sp.data(), sao->d_kp, h_n_feats, starts.data(), sao->d_work, s);
     if (e != hipSuccess) return fail(CHM_E_HIP, "SAO pair table upload failed: %s", hipGetErrorString(e));
+  }
+  if (ransac && total > 0) {
+    const int32_t n_max = *std::max_element(rows.begin(), rows.end());
+    if (ransac->work_bytes < ransac_work_bytes(total, n_max))
+      return fail(CHM_E_CAPACITY, "RANSAC work buffer too small");
+    const hipError_t e =
+        ransac_upload(total, sp.data(), sao->d_kp, h_n_feats, starts.data(), orig.data(), ransac->d_work, s);
+    if (e != hipSuccess) return fail(CHM_E_HIP, "RANSAC pair table upload failed: %s", hipGetErrorString(e));
   }
   // Two streams: descriptor copies on xs, everything else on the caller's
   // stream s.  The host queues step k+1 while the device runs step k:
@@ -284,6 +303,12 @@ chm_status run_schedule(chm_store* S, const chm_schedule* sc, const int32_t* h_p
                                    nullptr, sao->d_work, s);
       if (e != hipSuccess) return fail(CHM_E_HIP, "SAO launch failed: %s", hipGetErrorString(e));
     }
+    if (ransac && n > 0) {
+      const hipError_t e = ransac_run(f, n, total, rows[k], sao->d_filtered, ransac->d_words, ransac->iterations,
+                                      ransac->thr, ransac->min_inliers, ransac->d_verified, nullptr,
+                                      ransac->d_work, s);
+      if (e != hipSuccess) return fail(CHM_E_HIP, "RANSAC launch failed: %s", hipGetErrorString(e));
+    }
     if (verify && n > 0) {
       hipEvent_t ve = nullptr;
       if (hipEventCreateWithFlags(&ve, hipEventDisableTiming) != hipSuccess || hipEventRecord(ve, s) != hipSuccess) {
@@ -326,7 +351,8 @@ static chm_status run_schedule_sao(chm_store* S, const chm_schedule* sc, const i
                                    const void* const* h_descs, const int32_t* h_n_feats, int32_t n_images,
                                    const int64_t* h_offs, int32_t* d_out, const int32_t* const* d_kp,
                                    int32_t n_neighbors, int32_t score_num, int32_t score_den, int32_t* d_filtered,
-                                   void* d_work, uint64_t work_bytes, void* stream, const VerifyStep* verify) {
+                                   void* d_work, uint64_t work_bytes, void* stream, const VerifyStep* verify,
+                                   const RansacStep* ransac = nullptr) {
   if (!d_kp || !h_n_feats || !d_filtered || !d_work || d_filtered == d_out)
     return fail(CHM_E_INVALID_ARG, "bad SAO buffers");
   if (n_neighbors < 1 || n_neighbors > kSaoMaxNeighbors)
@@ -347,8 +373,19 @@ static chm_status run_schedule_sao(chm_store* S, const chm_schedule* sc, const i
   if (work_bytes < sao_work_bytes(P, n_max)) return fail(CHM_E_CAPACITY, "SAO work buffer too small");
   const hipError_t e = launch_fill_u32(static_cast<uint32_t*>(d_work), 0u, 1, (hipStream_t)stream);
   if (e != hipSuccess) return fail(CHM_E_HIP, "%s", hipGetErrorString(e));
+  if (ransac) {
+    if (!ransac->d_verified || !ransac->d_work || (ransac->iterations > 0 && !ransac->d_words))
+      return fail(CHM_E_INVALID_ARG, "bad RANSAC buffers");
+    if (ransac->iterations < 0 || ransac->thr < 0 || ransac->thr >= (1 << 20))
+      return fail(CHM_E_INVALID_ARG, "bad RANSAC parameters");
+    if (reinterpret_cast<uintptr_t>(ransac->d_work) % 256)
+      return fail(CHM_E_INVALID_ARG, "d_rwork must be 256-byte aligned");
+    if (ransac->work_bytes < ransac_work_bytes(P, n_max)) return fail(CHM_E_CAPACITY, "RANSAC work buffer too small");
+    const hipError_t e = launch_fill_u32(static_cast<uint32_t*>(ransac->d_work), 0u, 1, (hipStream_t)stream);
+    if (e != hipSuccess) return fail(CHM_E_HIP, "%s", hipGetErrorString(e));
+  }
   const SaoStep sao{d_kp, n_neighbors, score_num, score_den, d_filtered, d_work, work_bytes};
-  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao, verify);
+  return run_schedule(S, sc, h_pairs, P, h_descs, h_n_feats, h_offs, d_out, stream, &sao, verify, ransac);
 }
 
 extern "C" chm_status chm_run_schedule_sao(chm_store* S, const chm_schedule* sc, const int32_t* h_pairs,
@@ -379,6 +416,18 @@ extern "C" chm_status chm_run_schedule_verify(chm_store* S, const chm_schedule* 
   const VerifyStep v{h_kp, h_words, iterations, thr, min_inliers, n_threads, h_filtered, h_verified};
   return run_schedule_sao(S, sc, h_pairs, P, h_descs, h_n_feats, n_images, h_offs, d_out, d_kp, n_neighbors,
                           score_num, score_den, d_filtered, d_work, work_bytes, stream, &v);
+}
+
+extern "C" chm_status chm_run_schedule_verify_device(
+    chm_store* S, const chm_schedule* sc, const int32_t* h_pairs, int32_t P, const void* const* h_descs,
+    const int32_t* h_n_feats, int32_t n_images, const int64_t* h_offs, int32_t* d_out, const int32_t* const* d_kp,
+    int32_t n_neighbors, int32_t score_num, int32_t score_den, int32_t* d_filtered, void* d_work,
+    uint64_t work_bytes, const uint32_t* d_words, int32_t iterations, int32_t thr, int32_t min_inliers,
+    int32_t* d_verified, void* d_rwork, uint64_t rwork_bytes, void* stream) {
+  clear_error();
+  const RansacStep r{d_words, iterations, thr, min_inliers, d_verified, d_rwork, rwork_bytes};
+  return run_schedule_sao(S, sc, h_pairs, P, h_descs, h_n_feats, n_images, h_offs, d_out, d_kp, n_neighbors,
+                          score_num, score_den, d_filtered, d_work, work_bytes, stream, nullptr, &r);
 }
 
 extern "C" chm_status chm_bruteforce_work_bytes(int32_t nq, int32_t nd, uint64_t* out) {
