@@ -36,6 +36,9 @@ constexpr int kSaoBuildWG = 256;                   // build: one work-group per 
 constexpr int kSaoBuildWaves = kSaoBuildWG / 64;
 constexpr int kSaoMaxN = kSaoMaxNeighbors;
 constexpr int kSaoBatch = 512;  // pairs per launch pair (scratch is per pair)
+// grid density, points per cell on average (4 per cell: the same time on
+// the benchmark workload's matches; 8: 21% slower)
+constexpr double kSaoPointsPerCell = 2.0;
 constexpr int64_t kSaoCoordLimit = int64_t(1) << 30;
 constexpr int64_t kSaoSqrtMax = 3037000499LL;  // floor(sqrt(2^63 - 1))
 
@@ -74,17 +77,20 @@ __host__ __device__ inline uint64_t round16(uint64_t v) { return (v + 15) & ~uin
 __host__ __device__ inline int64_t sao_cells_max(int64_t n) { return 4 * n + 64; }
 
 // A pair's scratch for capacity n: info, rows[n], and per image pts[n]
-// (int4: x, y, compact index; in cell order) and cell[C + 1] (cell ends).
+// (int4: x, y, compact index; in cell order), cell[C + 1] (cell ends) and
+// xy[n] (the keypoint of each compact match: one load instead of three
+// dependent ones through rows, the matches and the keypoints).
 struct PairScratch {
   PairInfo* info;
   int32_t* rows;
   int4* pts[2];
   int32_t* cell[2];
+  int2* xy[2];
 };
 
 __host__ __device__ inline uint64_t pair_scratch_bytes(int64_t n) {
   const int64_t C = sao_cells_max(n);
-  return 128 + round16(4 * n) + 2 * (round16(16 * n) + round16(4 * (C + 1)));
+  return 128 + round16(4 * n) + 2 * (round16(16 * n) + round16(4 * (C + 1)) + round16(8 * n));
 }
 
 __device__ inline PairScratch scratch_at(const SaoArgs& a, int pair) {
@@ -100,6 +106,8 @@ __device__ inline PairScratch scratch_at(const SaoArgs& a, int pair) {
     p += round16(16 * n);
     s.cell[side] = reinterpret_cast<int32_t*>(p);
     p += round16(4 * (C + 1));
+    s.xy[side] = reinterpret_cast<int2*>(p);
+    p += round16(8 * n);
   }
   return s;
 }
@@ -345,6 +353,10 @@ __device__ inline int2 ldg_xy(const int32_t* p) {
   return make_int2(v.x, v.y);
 }
 
+__device__ inline int2 xy_at(const int2* xy, int32_t c) {
+  return ldg_xy(reinterpret_cast<const int32_t*>(xy + c));
+}
+
 // Keypoint of compact match c in image `side` (0 query, 1 db).
 __device__ inline int2 point_of(const SaoArgs& a, const SaoPair& P, const int32_t* rows, int side,
                                 int32_t c) {
@@ -396,6 +408,7 @@ __global__ __launch_bounds__(kSaoBuildWG) void k_sao_build(SaoArgs a) {
     int xmin = INT32_MAX, ymin = INT32_MAX, xmax = INT32_MIN, ymax = INT32_MIN;
     for (int c = tid; c < M; c += kSaoBuildWG) {
       const int2 q = point_of(a, P, S.rows, side, c);
+      S.xy[side][c] = q;
       if (q.x <= -kSaoCoordLimit || q.x >= kSaoCoordLimit || q.y <= -kSaoCoordLimit || q.y >= kSaoCoordLimit)
         s_bad = 1;
       xmin = min(xmin, q.x);
@@ -426,7 +439,7 @@ __global__ __launch_bounds__(kSaoBuildWG) void k_sao_build(SaoArgs a) {
         y1 = max(y1, (int64_t)s_red[3][w]);
       }
       const double w = double(x1 - x0) + 1.0, h = double(y1 - y0) + 1.0;
-      int64_t cell = max(int64_t(1), (int64_t)ceil(sqrt(w * h * 2.0 / double(M))));
+      int64_t cell = max(int64_t(1), (int64_t)ceil(sqrt(w * h * kSaoPointsPerCell / double(M))));
       int64_t nx, ny;
       for (;;) {  // at most 4 M + 64 cells, so the cell array always fits
         nx = (x1 - x0) / cell + 1;
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(kSaoBuildWG) void k_sao_build(SaoArgs a) {
     for (int64_t k = tid; k <= ncell; k += kSaoBuildWG) cell[k] = 0;
     phase_barrier();
     for (int c = tid; c < M; c += kSaoBuildWG) {
-      const int2 q = point_of(a, P, S.rows, side, c);
+      const int2 q = S.xy[side][c];
       const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
       const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
       atomicAdd(&cell[cy * g.nx + cx], 1);
@@ -463,7 +476,7 @@ __global__ __launch_bounds__(kSaoBuildWG) void k_sao_build(SaoArgs a) {
     // scatter; afterwards cell[k] is the end of cell k (the start of k + 1)
     int4* pts = S.pts[side];
     for (int c = tid; c < M; c += kSaoBuildWG) {
-      const int2 q = point_of(a, P, S.rows, side, c);
+      const int2 q = S.xy[side][c];
       const int64_t cx = min(max(((int64_t)q.x - g.x0) / g.cell, int64_t(0)), g.nx - 1);
       const int64_t cy = min(max(((int64_t)q.y - g.y0) / g.cell, int64_t(0)), g.ny - 1);
       const int32_t slot = atomicAdd(&cell[cy * g.nx + cx], 1);
@@ -497,7 +510,7 @@ __global__ __launch_bounds__(kSaoWG) void k_sao_search(SaoArgs a) {
     for (int side = 0; side < 2; ++side) {
       const GridInfo g = S.info->g[side];
       if (active) {
-        const int2 o = point_of(a, P, S.rows, side, c);
+        const int2 o = xy_at(S.xy[side], c);  // n > 0: M > 1, so the build wrote xy
         int32_t nn_idx[kSaoMaxN];
         const GlobalGrid G{S.cell[side], S.pts[side]};
         // packed keys when every coordinate difference is below 2^23
@@ -509,7 +522,7 @@ __global__ __launch_bounds__(kSaoWG) void k_sao_search(SaoArgs a) {
 #pragma unroll
         for (int k = 0; k < kSaoMaxN; ++k) {
           const int32_t nb = k < n ? min(max(nn_idx[k], 0), M - 1) : c;
-          const int2 q = point_of(a, P, S.rows, side, nb);
+          const int2 q = xy_at(S.xy[side], nb);
           e[k] = Polar{q.x - o.x, q.y - o.y, nb};
         }
         sort_by_angle(e, n);
