@@ -20,7 +20,9 @@
 // chunk by the lanes' bits in a per-wavefront LDS mask of each bucket (each
 // lane ORs its bit in: the rank is the count of lower lanes with the same
 // id), so the order inside a bucket is the descriptor order; the pads are
-// written last.
+// written last.  k_buckets_small does the same for images of up to
+// kSmallMaxN descriptors with the table assembled in LDS and written out
+// in whole 16-byte stores.
 //
 // k_tcodes: for images too large for the query-major kernel's LDS code
 // stage, the codes again in bucket order (tcodes[t][pos] = codes[j] for
@@ -163,6 +165,128 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
   for (int i = (int)s_total + tid; i < I.m_stride; i += kBucketWG) mem[i] = 0;
 }
 
+// Images up to kSmallMaxN descriptors: the same table built in LDS and
+// written out with whole 16-byte stores.  Scattering each member straight
+// to global memory (one 4-byte store per member, a different line per
+// lane) took about half of the kernel.  The counting pass also keeps each
+// member's rank inside its (wavefront, bucket) run, so the scatter needs no
+// second ranking.  Dynamic LDS: the ids, the ranks (2 B), then one region
+// that holds the peer masks during the counting pass and the bucket-ordered
+// members afterwards; with 16-bit counts the work-group stays within half a
+// CU's LDS.
+constexpr int kSmallMaxN = 8192;
+constexpr int kSmallMemMax = kSmallMaxN + 7 * 256;          // members per table, at most
+constexpr int kSmallRankOff = kSmallMaxN;                   // byte offsets in dynamic LDS
+constexpr int kSmallUnionOff = 3 * kSmallMaxN;
+constexpr int kSmallUnionBytes = (kBucketWaves * 256 * 8 > 4 * kSmallMemMax) ? kBucketWaves * 256 * 8
+                                                                             : 4 * kSmallMemMax;
+constexpr int kSmallDynBytes = kSmallUnionOff + kSmallUnionBytes;
+
+__global__ __launch_bounds__(kBucketWG) void k_buckets_small(HashBatch hb) {
+  extern __shared__ __attribute__((aligned(16))) uint8_t sDyn[];
+  __shared__ uint16_t cnt[kBucketWaves][256];
+  __shared__ uint32_t first[256];
+  __shared__ uint32_t real[256];
+  __shared__ uint32_t pbase[256];
+  __shared__ uint32_t s_total;
+  uint8_t* sId = sDyn;
+  uint16_t* sRank = reinterpret_cast<uint16_t*>(sDyn + kSmallRankOff);
+  unsigned long long(*peer)[256] = reinterpret_cast<unsigned long long(*)[256]>(sDyn + kSmallUnionOff);
+  uint32_t* sMem = reinterpret_cast<uint32_t*>(sDyn + kSmallUnionOff);
+
+  const int im = blockIdx.x / hb.L;
+  const int t = blockIdx.x % hb.L;
+  const HashImage I = hash_image(hb, im);
+  const int n = I.n;
+  const int nb = 1 << hb.m;
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = __lane_id();
+  const uint8_t* ids = I.ids + (size_t)t * I.n_pad;
+
+  for (int i = tid; i < I.n_pad / 8; i += kBucketWG)
+    reinterpret_cast<uint2*>(sId)[i] = reinterpret_cast<const uint2*>(ids)[i];
+  for (int i = tid; i < kBucketWaves * 256; i += kBucketWG) {
+    (&cnt[0][0])[i] = 0;
+    (&peer[0][0])[i] = 0ull;
+  }
+  for (int i = tid; i < 256; i += kBucketWG) first[i] = 0xFFFFFFFFu;
+  __syncthreads();
+
+  const int chunks = (n + 63) / 64;
+  const int per = (chunks + kBucketWaves - 1) / kBucketWaves;
+  const int c0 = wave * per, c1 = min(chunks, c0 + per);
+  const uint64_t lt = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  for (int c = c0; c < c1; ++c) {
+    const int i = c * 64 + lane;
+    const bool valid = i < n;
+    const uint32_t b = valid ? sId[i] : 0u;
+    const uint64_t peers = peers_of(peer[wave], b, valid);
+    if (valid) sRank[i] = (uint16_t)(cnt[wave][b] + (uint32_t)__popcll(peers & lt));
+    if (valid && (peers & lt) == 0) {  // after every peer has read the count (program order)
+      cnt[wave][b] = (uint16_t)(cnt[wave][b] + (uint32_t)__popcll(peers));
+      atomicMin(&first[b], (uint32_t)i);
+    }
+  }
+  __syncthreads();  // the peer masks are dead from here: the region holds the members
+
+  if (tid < 64) {
+    uint32_t tot[4], run = 0;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 4 * lane + k;
+      uint32_t s = 0;
+      if (b < nb)
+        for (int w = 0; w < kBucketWaves; ++w) s += cnt[w][b];
+      if (b < nb) {
+        real[b] = s;
+        I.counts[t * nb + b] = (int32_t)s;
+      }
+      tot[k] = (s + 7u) & ~7u;
+      run += tot[k];
+    }
+    uint32_t incl = run;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t v = __shfl_up(incl, d);
+      if (lane >= d) incl += v;
+    }
+    uint32_t base = incl - run;
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const int b = 4 * lane + k;
+      if (b < nb) {
+        I.offsets[t * (nb + 1) + b] = (int32_t)base;
+        pbase[b] = base;
+        uint32_t pos = base;
+        for (int w = 0; w < kBucketWaves; ++w) {
+          const uint32_t c = cnt[w][b];
+          cnt[w][b] = (uint16_t)pos;
+          pos += c;
+        }
+      }
+      base += tot[k];
+    }
+    if (lane == 63) {
+      I.offsets[t * (nb + 1) + nb] = (int32_t)incl;
+      s_total = incl;
+    }
+  }
+  __syncthreads();
+
+  // members into LDS: wavefront start in the bucket plus the rank; then the
+  // pads (copies of each bucket's first member) and the unused tail
+  for (int i = tid; i < n; i += kBucketWG) sMem[cnt[(i >> 6) / per][sId[i]] + sRank[i]] = 16u * (uint32_t)i;
+  for (int b = tid; b < nb; b += kBucketWG) {
+    const uint32_t c = real[b], pc = (c + 7u) & ~7u;
+    for (uint32_t k = c; k < pc; ++k) sMem[pbase[b] + k] = 16u * first[b];
+  }
+  for (int i = (int)s_total + tid; i < I.m_stride; i += kBucketWG) sMem[i] = 0;
+  __syncthreads();
+  uint4* mem = reinterpret_cast<uint4*>(I.members + (size_t)t * I.m_stride);  // m_stride: a multiple of 8
+  for (int i = tid; i < I.m_stride / 4; i += kBucketWG) mem[i] = reinterpret_cast<const uint4*>(sMem)[i];
+}
+
 // Bucket-ordered code copies.  Work-groups are dealt to the XCDs
 // round-robin; work-group w = x + n_xcd k (XCD x) copies slice k % slices
 // of batch image x + n_xcd (k / slices): entries [s kTcPer, (s + 1) kTcPer)
@@ -209,10 +333,15 @@ hipError_t launch_buckets(const HashBatch& hb, int n_xcd, hipStream_t s) {
   int n_pad = 8;
   for (int i = 0; i < hb.count; ++i) n_pad = max(n_pad, (hb.img[i].n + 7) / 8 * 8);
   if (n_pad > kBucketMaxN) return hipErrorInvalidValue;
-  hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_buckets),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, kBucketMaxN);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_buckets, dim3(hb.count * hb.L), dim3(kBucketWG), (size_t)n_pad, s, hb);
+  hipError_t e;
+  if (n_pad <= kSmallMaxN) {
+    hipLaunchKernelGGL(k_buckets_small, dim3(hb.count * hb.L), dim3(kBucketWG), (size_t)kSmallDynBytes, s, hb);
+  } else {
+    e = hipFuncSetAttribute(reinterpret_cast<const void*>(k_buckets), hipFuncAttributeMaxDynamicSharedMemorySize,
+                            kBucketMaxN);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k_buckets, dim3(hb.count * hb.L), dim3(kBucketWG), (size_t)n_pad, s, hb);
+  }
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   int slices = 0;
