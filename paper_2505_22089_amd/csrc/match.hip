@@ -16,7 +16,9 @@
 //      candidate list a set (a key equal to the last kept one leaves the
 //      list unchanged, so it needs no test).  Keys of a block of eight
 //      candidates are computed first; only those below the current KT-th
-//      key are inserted, one per lane per round, selected with wave masks;
+//      key are inserted, one per lane per round, selected with wave masks.
+//      The walk's first blocks, while every lane is in its first bucket
+//      (where only pads can repeat a key), are sorted and merged whole;
 //  (4) for the first K kept candidates it computes the exact squared distance
 //      ||x||^2 + ||y||^2 - 2 x.y with packed-u8 dot products and int32
 //      accumulation, and applies the ratio test on squared distances
@@ -41,6 +43,45 @@
 #include "match_common.h"
 
 namespace chm {
+
+// Blocks of a walk merged whole into the kept list (KT = 8) while every
+// lane is in its first bucket: the first and up to this many - 1 more.
+constexpr int kMergeBlocks = 3;
+
+// Ascending sort of 8 keys: Batcher's odd-even merge network, 19
+// compare-exchanges in 6 layers.
+__device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
+  auto ce = [&](int i, int j) {
+    const uint32_t lo = min(v[i], v[j]), hi = max(v[i], v[j]);
+    v[i] = lo;
+    v[j] = hi;
+  };
+  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
+  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
+  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
+  ce(2, 4); ce(3, 5);
+  ce(1, 4); ce(3, 6);
+  ce(1, 2); ce(3, 4); ce(5, 6);
+}
+
+// The 8 smallest of the ascending lists a and b, ascending, into a:
+// min(a[k], b[7 - k]) is a bitonic sequence holding them, which three
+// half-cleaner layers sort.
+__device__ __forceinline__ void merge8_lowest(uint32_t (&a)[8], const uint32_t (&b)[8]) {
+  uint32_t m[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m[k] = min(a[k], b[7 - k]);
+  auto ce = [&](int i, int j) {
+    const uint32_t lo = min(m[i], m[j]), hi = max(m[i], m[j]);
+    m[i] = lo;
+    m[j] = hi;
+  };
+  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
+  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
+  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = m[k];
+}
 
 // Called by all 64 lanes of the wavefront (the re-rank is cooperative);
 // a lane with valid false owns no query (q is any valid index) and writes
@@ -160,15 +201,54 @@ __device__ __forceinline__ void match_query(const MatchArgs& a, const PairDev& P
     uint4 A0, A1, B0, B1;
     uint32_t offA, offB;
     load(A0, A1, offA, cur);
+    // While every lane of the wave is still in its first bucket, a block
+    // needs no insertion rounds: the members of one bucket are distinct, so
+    // the only keys that can repeat a kept one are pads (copies of the
+    // bucket's first member w0), which are masked; the block's keys are
+    // sorted and merged with the list whole.  The walk's first block (an
+    // empty list) is done so for KT < 8, kMergeBlocks blocks for KT = 8.
+    const int t0 = t;
+    int tA = t0, tB = t0;
+    int merge_left = KT == 8 ? kMergeBlocks : KT < 8 ? 1 : 0;  // (longer lists: registers)
+    bool first = true;
+    uint32_t w0 = 0;
+    auto merge = [&](const uint4& x0, const uint4& x1, bool valid, int tblk) {
+      if (merge_left <= 0) return;
+      if (__ballot(valid && tblk != t0) != 0) {
+        merge_left = 0;
+        return;
+      }
+      --merge_left;
+      const uint32_t w[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+      if (first) w0 = w[0];
+      uint32_t v[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) v[k] = (!valid || (w[k] == w0 && (k > 0 || !first))) ? kNoKey : pkey[k];
+      sort8(v);
+      if constexpr (KT == 8) {
+        merge8_lowest(top, v);
+      } else {
+#pragma unroll
+        for (int k = 0; k < KT; ++k) top[k] = k < 8 ? v[k & 7] : kNoKey;
+      }
+      first = false;
+      thr = top[KT - 1];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) ppass[k] = 0;
+    };
     for (;;) {
       const bool nb = cur && advance();
       load(B0, B1, offB, nb);
+      tB = t;
       step(A0, A1, offA, cur);
+      merge(A0, A1, cur, tA);
       cur = nb;
       if (__ballot(cur) == 0) break;
       const bool na = cur && advance();
       load(A0, A1, offA, na);
+      tA = t;
       step(B0, B1, offB, cur);
+      merge(B0, B1, cur, tB);
       cur = na;
       if (__ballot(cur) == 0) break;
     }

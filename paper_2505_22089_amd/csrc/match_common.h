@@ -46,12 +46,25 @@ __device__ __forceinline__ uint4 ldg4(const void* p) {
   return make_uint4(v.x, v.y, v.z, v.w);
 }
 
+__device__ __forceinline__ uint32_t min3u(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_min3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "v"(c));
+  return r;
+}
+
+// Inserts key into the ascending list top unless it repeats a kept key (a
+// key equal to the last one changes nothing, so only the first KT - 1 are
+// tested): the smallest XOR of key with them is zero exactly for a repeat.
+// The test stays in VALU registers; equality compares would build a lane
+// mask through the scalar unit, one dependent round trip per kept key.
 template <int KT>
 __device__ __forceinline__ void insert_unique(uint32_t (&top)[KT], uint32_t key) {
-  bool dup = false;
+  uint32_t m = key ^ top[0];
+  int k = 1;
 #pragma unroll
-  for (int k = 0; k < KT - 1; ++k) dup |= (key == top[k]);
-  key = dup ? kNoKey : key;
+  for (; k + 1 < KT - 1; k += 2) m = min3u(m, key ^ top[k], key ^ top[k + 1]);
+  if (k < KT - 1) m = min(m, key ^ top[k]);
+  key = m == 0u ? kNoKey : key;
 #pragma unroll
   for (int k = KT - 1; k >= 1; --k) top[k] = med3u(top[k - 1], key, top[k]);
   top[0] = min(top[0], key);
