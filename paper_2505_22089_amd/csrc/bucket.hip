@@ -115,12 +115,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets(HashBatch hb) {
       tot[k] = (s + 7u) & ~7u;
       run += tot[k];
     }
-    uint32_t incl = run;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
+    const uint32_t incl = wave_incl_add(run);
     uint32_t base = incl - run;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
@@ -245,12 +240,7 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets_small(HashBatch hb) {
       tot[k] = (s + 7u) & ~7u;
       run += tot[k];
     }
-    uint32_t incl = run;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t v = __shfl_up(incl, d);
-      if (lane >= d) incl += v;
-    }
+    const uint32_t incl = wave_incl_add(run);
     uint32_t base = incl - run;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

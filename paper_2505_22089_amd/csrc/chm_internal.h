@@ -11,6 +11,22 @@ constexpr int kCodeWords = 4;   // 128-bit long code as 4 x u32
 constexpr int kRowsPad = 192;   // projection rows padded: 128 code + up to 64 bucket bits
 constexpr uint32_t kNoKey = 0xFFFFFFFFu;
 
+#if defined(__HIPCC__)
+// Inclusive prefix sum over the 64 lanes of a wavefront by DPP (no LDS
+// round trips): running sums inside each 16-lane row, then the totals of
+// rows 0 and 2 into rows 1 and 3, then the total of rows 0-1 into rows 2-3.
+// Called with every lane active.
+__device__ __forceinline__ uint32_t wave_incl_add(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true);   // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true);   // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true);   // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true);   // row_shr:8
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false);  // row_bcast:15
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false);  // row_bcast:31
+  return v;
+}
+#endif
+
 // Device-side view of one resident image.
 struct ImageDev {
   const uint8_t* desc;      // n x 128

@@ -445,12 +445,7 @@ __device__ __forceinline__ void sort_item(const MatchArgs& a, const PairDev& P, 
       v[k] = s.hist[4 * lane + k];
       run += v[k];
     }
-    uint32_t incl = run;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-      const uint32_t u = __shfl_up(incl, d);
-      if (lane >= d) incl += u;
-    }
+    const uint32_t incl = wave_incl_add(run);
     uint32_t base = incl - run;
 #pragma unroll
     for (int k = 0; k < 4; ++k) {

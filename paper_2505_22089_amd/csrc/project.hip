@@ -207,8 +207,20 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
     }
     // the tile's largest ||x|| (rounded up), then each row's threshold
     float sx = valid ? sqrtf((float)nx) * 1.000001f : 0.f;
-#pragma unroll
-    for (int o = 1; o < 32; o <<= 1) sx = fmaxf(sx, __shfl_xor(sx, o));
+    {
+      // the largest over the 64 lanes (each half holds the tile's 32
+      // norms) by DPP: running maxima inside each 16-lane row, then across
+      // rows, read from lane 63; sx >= 0, so its bit pattern orders like
+      // the value
+      uint32_t v = __float_as_uint(sx);
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xF, 0xF, true));   // row_shr:1
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xF, 0xF, true));   // row_shr:2
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xF, 0xF, true));   // row_shr:4
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xF, 0xF, true));   // row_shr:8
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x142, 0xA, 0xF, false));  // row_bcast:15
+      v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x143, 0xC, 0xF, false));  // row_bcast:31
+      sx = __uint_as_float((uint32_t)__builtin_amdgcn_readlane((int)v, 63));
+    }
     for (int r = lane; r < kRowsPad; r += 64)
       sThr[wave][r] = r < R ? fmaxf(fmaf(sRow[0][r], sx, sRow[1][r]), 1e-30f) : -1.f;
     wave_sync();

@@ -116,12 +116,7 @@ __device__ inline PairScratch scratch_at(const SaoArgs& a, int pair) {
 template <int WAVES>
 __device__ inline int block_exclusive(int v, int* s_tmp, int* total) {
   const int lane = __lane_id(), wave = threadIdx.x >> 6;
-  int incl = v;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    const int u = __shfl_up(incl, d);
-    if (lane >= d) incl += u;
-  }
+  const int incl = (int)wave_incl_add((uint32_t)v);
   if (lane == 63) s_tmp[wave] = incl;
   __syncthreads();
   int before = 0, sum = 0;
