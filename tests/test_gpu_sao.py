@@ -67,6 +67,26 @@ def test_device_sao_matches_oracle(nn, th):
         assert np.array_equal(out[offs[p]:offs[p + 1]], rf), p
 
 
+def test_device_sao_large_and_small_pairs_in_one_call():
+    """A pair with over 5,000 matches beside small ones, in one call (one
+    search launch covers work-groups of very different sizes): CED and
+    verdicts equal the oracle's."""
+    cases = [_pair_case(21, n_q=9000, n_d=8000), _pair_case(22), _pair_case(23, n_q=3000, n_d=2500)]
+    kps, pairs, parts = [], [], []
+    for kq, kd, m in cases:
+        pairs.append((len(kps), len(kps) + 1))
+        kps += [kq, kd]
+        parts.append(m)
+    assert (parts[0] >= 0).sum() > 5000
+    offs = np.concatenate([[0], np.cumsum([len(m) for m in parts])]).astype(np.int64)
+    out, ced, bad = _run_device(kps, np.array(pairs), offs, np.concatenate(parts), 6, (1, 2))
+    assert bad == 0
+    for p, (kq, kd, m) in enumerate(cases):
+        rc, rf = S.sao_pair(kq, kd, m, 6, (1, 2))
+        assert np.array_equal(ced[offs[p]:offs[p + 1]], rc), p
+        assert np.array_equal(out[offs[p]:offs[p + 1]], rf), p
+
+
 def test_device_sao_degenerate_layouts():
     # collinear points, all points on one spot, a thin strip, huge spread
     rng = np.random.default_rng(20)
