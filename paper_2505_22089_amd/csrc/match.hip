@@ -48,41 +48,6 @@ namespace chm {
 // lane is in its first bucket: the first and up to this many - 1 more.
 constexpr int kMergeBlocks = 3;
 
-// Ascending sort of 8 keys: Batcher's odd-even merge network, 19
-// compare-exchanges in 6 layers.
-__device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
-  auto ce = [&](int i, int j) {
-    const uint32_t lo = min(v[i], v[j]), hi = max(v[i], v[j]);
-    v[i] = lo;
-    v[j] = hi;
-  };
-  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
-  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
-  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
-  ce(2, 4); ce(3, 5);
-  ce(1, 4); ce(3, 6);
-  ce(1, 2); ce(3, 4); ce(5, 6);
-}
-
-// The 8 smallest of the ascending lists a and b, ascending, into a:
-// min(a[k], b[7 - k]) is a bitonic sequence holding them, which three
-// half-cleaner layers sort.
-__device__ __forceinline__ void merge8_lowest(uint32_t (&a)[8], const uint32_t (&b)[8]) {
-  uint32_t m[8];
-#pragma unroll
-  for (int k = 0; k < 8; ++k) m[k] = min(a[k], b[7 - k]);
-  auto ce = [&](int i, int j) {
-    const uint32_t lo = min(m[i], m[j]), hi = max(m[i], m[j]);
-    m[i] = lo;
-    m[j] = hi;
-  };
-  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
-  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
-  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
-#pragma unroll
-  for (int k = 0; k < 8; ++k) a[k] = m[k];
-}
-
 // Called by all 64 lanes of the wavefront (the re-rank is cooperative);
 // a lane with valid false owns no query (q is any valid index) and writes
 // nothing.

@@ -166,6 +166,36 @@ __global__ __launch_bounds__(64) void k_match_bm(BmArgs a) {
     // The bucket's members as aligned blocks of 8 (pads repeat the first
     // member); member value 16 j is the byte offset of db point j's code.
     const uint32_t lim_on = valid ? 1u : 0u;
+    if constexpr (FIRST && KT == 8) {
+      // Table 0: every candidate is a member of this one bucket, so no key
+      // can repeat a kept one except the pads (copies of member 0, the same
+      // slots in every lane); each block's keys, pads masked, are sorted and
+      // merged with the list whole, with no insertion rounds.
+      const uint32_t m0 = nblk > 0 ? ld_uniform(dmem) : 0u;
+      for (int blk = 0; blk < nblk; ++blk) {
+        uint32_t mv[8];
+        uint4 cv[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) mv[kk] = ld_uniform(dmem + 8 * blk + kk);
+        if (dtc) {
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) cv[kk] = ld_uniform4(dtc + 8 * blk + kk);
+        } else {
+#pragma unroll
+          for (int kk = 0; kk < 8; ++kk) cv[kk] = ld_uniform4(dcodes + mv[kk]);
+        }
+        uint32_t v[8];
+#pragma unroll
+        for (int kk = 0; kk < 8; ++kk) {
+          const uint32_t h = bcnt_acc(qc.w ^ cv[kk].w,
+                                      bcnt_acc(qc.z ^ cv[kk].z, bcnt_acc(qc.y ^ cv[kk].y, bcnt_acc(qc.x ^ cv[kk].x, 0u))));
+          const bool pad = mv[kk] == m0 && (blk > 0 || kk > 0);  // uniform
+          v[kk] = pad ? kNoKey : (h << 24) | mv[kk];
+        }
+        sort8(v);
+        merge8_lowest(top, v);
+      }
+    } else {
     for (int blk = 0; blk < nblk; ++blk) {
       uint32_t mv[8];
       uint4 cv[8];
@@ -189,6 +219,7 @@ __global__ __launch_bounds__(64) void k_match_bm(BmArgs a) {
       }
     }
     drain();
+    }
 
     if (!LAST) {
       if (valid) state_store<KT>(a.state, row, top);

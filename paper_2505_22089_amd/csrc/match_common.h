@@ -70,6 +70,41 @@ __device__ __forceinline__ void insert_unique(uint32_t (&top)[KT], uint32_t key)
   top[0] = min(top[0], key);
 }
 
+// Ascending sort of 8 keys: Batcher's odd-even merge network, 19
+// compare-exchanges in 6 layers.
+__device__ __forceinline__ void sort8(uint32_t (&v)[8]) {
+  auto ce = [&](int i, int j) {
+    const uint32_t lo = min(v[i], v[j]), hi = max(v[i], v[j]);
+    v[i] = lo;
+    v[j] = hi;
+  };
+  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
+  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
+  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
+  ce(2, 4); ce(3, 5);
+  ce(1, 4); ce(3, 6);
+  ce(1, 2); ce(3, 4); ce(5, 6);
+}
+
+// The 8 smallest of the ascending lists a and b, ascending, into a:
+// min(a[k], b[7 - k]) is a bitonic sequence holding them, which three
+// half-cleaner layers sort.
+__device__ __forceinline__ void merge8_lowest(uint32_t (&a)[8], const uint32_t (&b)[8]) {
+  uint32_t m[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) m[k] = min(a[k], b[7 - k]);
+  auto ce = [&](int i, int j) {
+    const uint32_t lo = min(m[i], m[j]), hi = max(m[i], m[j]);
+    m[i] = lo;
+    m[j] = hi;
+  };
+  ce(0, 4); ce(1, 5); ce(2, 6); ce(3, 7);
+  ce(0, 2); ce(1, 3); ce(4, 6); ce(5, 7);
+  ce(0, 1); ce(2, 3); ce(4, 5); ce(6, 7);
+#pragma unroll
+  for (int k = 0; k < 8; ++k) a[k] = m[k];
+}
+
 typedef __attribute__((address_space(3))) const v4u lds_v4u;
 
 // Long code of the db point whose code lies at byte offset off (16 j): in
