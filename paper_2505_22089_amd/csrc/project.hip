@@ -30,7 +30,8 @@
 // row r lands on bit r; the borderline flags (the sign of |p| minus the
 // threshold) go into a second word the same way.  Borderline (descriptor,
 // row) entries go to the wavefront's own region of a global list (offsets
-// from a per-wavefront LDS counter).  After the last tile the work-group recomputes the entries of its
+// from a running wave-uniform count plus a DPP prefix sum over the
+// lanes).  After the last tile the work-group recomputes the entries of its
 // regions in fp64 and patches the bits with 32-bit atomics.  A region that
 // overflowed (adversarial inputs only) is not read: its wavefront rebuilds
 // every code and bucket id of its tiles from exact values instead.
@@ -126,7 +127,7 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
   __shared__ uint16_t sW[kRowsPad * kWStrideX];
   __shared__ float sThr[kProjWaves][kRowsPad];  // the current tile's threshold of each row
   __shared__ float sRow[3][kRowsPad];           // tau_r, kappa_r, c_r (fp32)
-  __shared__ uint32_t sCount[kProjWaves];       // entries each wavefront listed (LDS atomics)
+  __shared__ uint32_t sCount[kProjWaves];       // entries each wavefront listed
   __shared__ unsigned long long sSum[2];        // the work-group's fix-ups and changed bits
 
   const int tid = threadIdx.x;
@@ -151,7 +152,6 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
     dst[0] = v.x; dst[1] = v.y; dst[2] = v.z; dst[3] = v.w;
   }
   if (tid < 2) sSum[tid] = 0;
-  if (tid < kProjWaves) sCount[tid] = 0;
   __syncthreads();
 
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);  // uniform: keeps tile / image in SGPRs
@@ -169,7 +169,8 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
   // this wavefront's region of the fix-up list: [gw * cap_w, (gw + 1) * cap_w)
   const uint32_t gw = blockIdx.x * kProjWaves + wave;
   const uint32_t cap_w = pc.fix_cap / pc.n_waves;
-  uint32_t* region = pc.fixlist + (size_t)gw * cap_w;  // sCount[wave] entries listed so far
+  uint32_t* region = pc.fixlist + (size_t)gw * cap_w;
+  uint32_t wcnt = 0;  // entries this wavefront listed so far (uniform; sCount[wave] after the tiles)
 
   const int total_tiles = hb.tile_prefix[hb.count];
   const int tile_step = gridDim.x * kProjWaves;
@@ -283,19 +284,23 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
       // borderline entries of this half's rows (rows >= R have threshold -1
       // and are never flagged) go to the wavefront's region
       bd = valid ? (bd & own) : 0u;
-      if (bd) {
-        uint32_t idx = atomicAdd(&sCount[wave], (uint32_t)__popc(bd));
-        do {
+      if (__ballot(bd != 0u)) {  // consecutive slots: a DPP prefix sum of the lanes' counts
+        const uint32_t nb = (uint32_t)__popc(bd);
+        const uint32_t incl = wave_incl_add(nb);
+        uint32_t idx = wcnt + incl - nb;
+        wcnt += (uint32_t)__builtin_amdgcn_readlane((int)incl, 63);
+        while (bd) {
           const int bit = __builtin_ctz(bd);
           bd &= bd - 1u;
           if (idx < cap_w) region[idx] = ((uint32_t)im << 24) | ((uint32_t)(32 * blk + bit) << 16) | (uint32_t)dr;
           ++idx;
-        } while (bd);
+        }
       }
     }
     if (h == 0 && valid) I.norms[dr] = nx;
     wave_sync();  // sThr is rewritten by the next tile
   }
+  if (lane == 0) sCount[wave] = wcnt;
 
   // Fix-up of the work-group's listed entries (regions concatenated in
   // wavefront order; a region that overflowed counts as empty), 64 entries
