@@ -241,7 +241,7 @@ chm_status chm_match_pairs(chm_store *store, const int32_t *h_pairs, int32_t n_p
  * valid value gives identical results). */
 typedef struct chm_tuning {
   int32_t queries_per_item; /* queries per batched work item, multiple of 64,
-                               64..8192 (default 3072).  Batched plans shrink
+                               64..8192 (default 2048).  Batched plans shrink
                                items where a larger one would not sort in LDS,
                                cap them at 512 in launches that stage no db
                                image, and halve those ending each XCD bin's

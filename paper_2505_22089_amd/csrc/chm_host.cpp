@@ -232,7 +232,7 @@ extern "C" chm_status chm_store_create(const chm_config* cfg, const uint16_t* h_
   S->dFix = (unsigned long long*)(S->base + kHdrFix);
   S->dFixList = (uint32_t*)(S->base + kHdrFixList);
   std::memset(&S->stats, 0, sizeof S->stats);
-  S->tuning.queries_per_item = 3072;
+  S->tuning.queries_per_item = 2048;
   S->tuning.wg_threads = 1024;
   S->tuning.lds_codes = 1;
   S->tuning.grid_per_cu = 1;
