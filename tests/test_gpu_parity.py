@@ -42,12 +42,13 @@ def check_hash(store, wl, ids):
         assert np.array_equal(g["norms"].astype(np.int64), (x * x).sum(1))
 
 
-def test_hash_parity_table_kernels_at_the_lds_limit():
+@pytest.mark.parametrize("L,m", [(6, 8), (3, 5)])
+def test_hash_parity_table_kernels_at_the_lds_limit(L, m):
     """Bucket tables of a batch whose largest image has 8,192 features (built
     in LDS), then of one with 8,193 (scattered to global memory): both equal
     the oracle's, and so does a later rehash of all three images together."""
-    wl = small_workload([8192, 8191, 8193], seed=5)
-    st = new_store(wl)
+    wl = small_workload([8192, 8191, 8193], seed=5 + m)
+    st = new_store(wl, L=L, m=m)
     load_all(st, wl.images[:2])
     check_hash(st, wl, [0, 1])
     load_all(st, wl.images, ids=[2])
