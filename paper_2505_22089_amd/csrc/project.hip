@@ -227,7 +227,9 @@ __global__ __launch_bounds__(kProjWG, FP32 ? 2 : CHM_PROJ_WAVES_PER_SIMD) void k
     wave_sync();
 
     uint32_t w4 = 0u;  // block 4's word, kept for the bucket ids
-#pragma unroll 1
+    // unrolled: the scheduler may start a block's W reads and MFMA chain
+    // beside the previous block's epilogue
+#pragma unroll
     for (int blk = 0; blk < 6; ++blk) {
       f32x16 acc;
 #pragma unroll
