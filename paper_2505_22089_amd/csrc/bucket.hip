@@ -282,8 +282,9 @@ __global__ __launch_bounds__(kBucketWG) void k_buckets_small(HashBatch hb) {
 // of batch image x + n_xcd (k / slices): entries [s kTcPer, (s + 1) kTcPer)
 // of its L x m_stride.  All slices of an image thus run on one XCD, whose
 // L2 holds the image's codes for the gathers.  Images without a copy, and
-// work-groups past the batch, return at once.  A thread takes 4 consecutive
-// entries: one 16-byte load of their members, 4 code gathers, 4 stores.
+// work-groups past the batch, return at once.  A thread takes groups of 4
+// consecutive entries (one 16-byte load of their members, 4 code gathers,
+// 4 stores), two groups per pass.
 constexpr int kTcWG = 256;
 constexpr int kTcPer = 8192;
 
@@ -298,7 +299,30 @@ __global__ __launch_bounds__(kTcWG) void k_tcodes(HashBatch hb, int slices, int 
   const uint32_t s0 = (uint32_t)(k % slices) * (uint32_t)kTcPer;
   const uint32_t s1 = min(total, s0 + (uint32_t)kTcPer);
   const char* codes = reinterpret_cast<const char*>(I.codes);
-  for (uint32_t pos = s0 + 4 * threadIdx.x; pos < s1; pos += 4 * kTcWG) {
+  // two groups of 4 entries per pass (both member loads, then the eight
+  // gathers, then the stores), then one left over
+  uint32_t pos = s0 + 4 * threadIdx.x;
+  for (; pos + 4 * kTcWG < s1; pos += 8 * kTcWG) {
+    const uint4 m = *reinterpret_cast<const uint4*>(I.members + pos);
+    const uint4 n = *reinterpret_cast<const uint4*>(I.members + pos + 4 * kTcWG);
+    const uint4 c0 = *reinterpret_cast<const uint4*>(codes + m.x);
+    const uint4 c1 = *reinterpret_cast<const uint4*>(codes + m.y);
+    const uint4 c2 = *reinterpret_cast<const uint4*>(codes + m.z);
+    const uint4 c3 = *reinterpret_cast<const uint4*>(codes + m.w);
+    const uint4 d0 = *reinterpret_cast<const uint4*>(codes + n.x);
+    const uint4 d1 = *reinterpret_cast<const uint4*>(codes + n.y);
+    const uint4 d2 = *reinterpret_cast<const uint4*>(codes + n.z);
+    const uint4 d3 = *reinterpret_cast<const uint4*>(codes + n.w);
+    I.tcodes[pos] = c0;
+    I.tcodes[pos + 1] = c1;
+    I.tcodes[pos + 2] = c2;
+    I.tcodes[pos + 3] = c3;
+    I.tcodes[pos + 4 * kTcWG] = d0;
+    I.tcodes[pos + 4 * kTcWG + 1] = d1;
+    I.tcodes[pos + 4 * kTcWG + 2] = d2;
+    I.tcodes[pos + 4 * kTcWG + 3] = d3;
+  }
+  if (pos < s1) {
     const uint4 m = *reinterpret_cast<const uint4*>(I.members + pos);
     const uint4 c0 = *reinterpret_cast<const uint4*>(codes + m.x);
     const uint4 c1 = *reinterpret_cast<const uint4*>(codes + m.y);
